@@ -1,0 +1,198 @@
+"""Benchmark of the AR-OAM hot path on one MI355X: LSQR-Tikhonov reconstructions of the
+200x200-position workload (voxels 200x200x128 at 10 um, Nt 512, cone footprint up to 41x41
+offsets, 50 iterations).  One step = one full reconstruction (50 iterations = 50 A + 50 A^T
+applies plus the initial A^T, with the fused FP64 vector work).  Prints one JSON line.
+
+Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "A+Aᵀ applies/s (TMAC/s, % MFMA peak); recon p50/p99 latency vs plain FP32"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp64": 78.6}
+DTYPE_TAG = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8", "fp64": "f64"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_times(model, dtype, x, s, reps):
+    """Average duration (ms) of one forward and one adjoint launch, timed with HIP events on
+    the stream the library launches on (torch's current stream)."""
+    import torch
+    st = torch.cuda.current_stream()
+    out = {}
+    for name, fn, arg in (("forward", model.forward, x), ("adjoint", model.adjoint, s)):
+        fn(arg, dtype)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(reps):
+            fn(arg, dtype)
+        e1.record(st)
+        e1.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def cpu_baseline(cfg, mac_full, depths=(40, 41, 86, 87)):
+    """The FP64 oracle's A + A^T pair on a bounded sample of the same workload: the full scan
+    grid and footprint restricted to a few depth slabs, scaled to full-workload pairs/s by the
+    ratio of algorithmic MACs."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import workloads as W
+    from oracle import model as omodel
+    from oracle import operators as oops
+    g = cfg["grid"]
+    ks = list(depths)
+    t0 = time.time()
+    H = omodel.build_table(cfg["sensor"], g, depths=ks)[:, :, ks, :]
+    t_table = time.time() - t0
+    nzr = H != 0                                  # [dy, dx, slab, n]
+    present = nzr.any(axis=-1)
+    first = np.argmax(nzr, axis=-1)
+    last = g["nt"] - 1 - np.argmax(nzr[..., ::-1], axis=-1)
+    length = np.where(present, last - first + 1, 0)
+    K = g["k_half"]
+    d = np.abs(np.arange(-K, K + 1))
+    pairs = (g["ny"] - d)[:, None] * (g["nx"] - d)[None, :]
+    mac_sample = int(np.sum(pairs[:, :, None] * length))
+    rng = W.rng(99)
+    x = rng.standard_normal((g["ny"], g["nx"], len(ks)))
+    y = rng.standard_normal((g["ny"], g["nx"], g["nt"]))
+    times = []
+    for _ in range(2):
+        t0 = time.time()
+        oops.forward(H, x)
+        oops.adjoint(H, y)
+        times.append(time.time() - t0)
+    t_pair = min(times)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()
+                   if d.get("user_api") == "blas"] or [1])
+    frac = mac_sample / mac_full
+    return dict(value=frac / t_pair, unit="A+A^T pairs/s", cores=int(threads), kind="oracle",
+                sample=(f"FP64 oracle A+A^T pair on depth slabs {ks} of the full 200x200 scan "
+                        f"({100 * frac:.2f}% of the algorithmic MACs), {t_pair:.2f} s per sample "
+                        f"pair, scaled by the MAC ratio; table build for the slabs "
+                        f"{t_table:.1f} s not included"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="vessels200")
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2009_10173_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    cfg = W.config(args.workload)
+    g = cfg["grid"]
+    iters = cfg["solver"]["iters"]
+    log(f"building model {args.workload}")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    model = P.Model(cfg["sensor"], g, dtypes=("fp32", "bf16"))
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    info = model.info()
+    log(f"model built in {t_build:.2f} s: nnz {info['nnz']}, MAC_alg {info['mac_alg']:.3e}")
+
+    x0 = torch.from_numpy(W.make_phantom(cfg, 0).astype(np.float32)).to(dev)
+    clean = model.forward(x0, "fp32")
+    sigma = clean.abs().max().item() * 10 ** (-cfg["snr_db"] / 20)
+    s = clean + sigma * torch.from_numpy(W.unit_noise(cfg, 0).astype(np.float32)).to(dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return model.solve_lsqr(s, lam=-1.0, iters=iters, inner=args.dtype)
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t1 = time.perf_counter()
+        x, sinfo = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+        log(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
+    elapsed = time.perf_counter() - t_start
+    pairs_per_step = iters + 0.5          # 50 A + 50 A^T + the initial A^T
+    pairs_s = args.steps * pairs_per_step / elapsed
+
+    kt = kernel_times(model, args.dtype, x0, s, args.kernel_reps)
+    dom = max(kt, key=kt.get)
+    di = P.DTYPES[args.dtype]
+    mac_exec = info["mac_exec"][di] if dom == "forward" else info["mac_exec_adj"][di]
+    flops = 2.0 * info["mac_alg"]
+    achieved = flops / (kt[dom] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.dtype]
+    mfma_issued = 2.0 * mac_exec / (kt[dom] * 1e-3) / 1e12
+    result = {
+        "metric": METRIC,
+        "value": pairs_s,
+        "unit": "A+A^T pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE_TAG[args.dtype],
+        "data": "synthetic",
+        "config": {"workload": (f"{args.workload}: LSQR-Tikhonov {iters} its, scan "
+                                f"{g['nx']}x{g['ny']} at {g['step_m'] * 1e6:g} um, voxels "
+                                f"{g['nx']}x{g['ny']}x{g['nz']}, Nt {g['nt']}, cone footprint "
+                                f"K={g['k_half']}, 40 curved-tube phantom, 20 dB"),
+                   "solver": "lsqr", "iters": iters},
+        "tmac_s": 2.0 * info["mac_alg"] * pairs_s / 1e12,
+        "recon_ms_p50": float(np.percentile(lat, 50) * 1e3),
+        "recon_ms_p99": float(np.percentile(lat, 99) * 1e3),
+        "kernel_ms": kt,
+        "fill": {"forward": info["mac_alg"] / info["mac_exec"][di],
+                 "adjoint": info["mac_alg"] / info["mac_exec_adj"][di]},
+        "table_build_s": t_build,
+        "lambda": sinfo["lam"],
+        "roofline": {"bound": "mfma", "kernel": f"{dom} ({args.dtype} MFMA)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "issued_frac": mfma_issued / peak,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(cfg, info["mac_alg"])
+    model.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

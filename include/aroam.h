@@ -1,0 +1,191 @@
+/*
+ * aroam.h - C ABI of the MI355X (gfx950) model-based AR-OAM reconstruction library.
+ *
+ * Model-based inversion for acoustic-resolution optoacoustic microscopy with a raster-scanned
+ * spherical sensor (Li, Hofmann et al., "Broadband model-based inversion enables optoacoustic
+ * microscopy beyond the acoustic diffraction limit").  The library builds the compressed,
+ * scan-symmetric time-domain model, applies it and its transpose, and solves Eq. 5 with LSQR
+ * (Tikhonov, Eq. 6) or FISTA (L1, Eq. 7).  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions shared by all calls
+ *   - Return value: AROAM_OK (0) or a negative aroam_status.  aroam_last_error() returns a
+ *     message for the calling thread's last failure (valid until that thread's next call).
+ *   - Vectors are DEVICE pointers owned by the caller, C-contiguous:
+ *       image   x[ny][nx][nz]  (voxel columns; depth fastest)
+ *       signals s[ny][nx][nt]  (one time trace per scan position; time fastest)
+ *     The voxel lateral grid coincides with the scan grid (Results, first paragraph).
+ *     Element type: double for AROAM_FP64, float for every other dtype (AROAM_BF16 and
+ *     AROAM_FP8E4M3 name the precision of the model table and operands inside the apply;
+ *     accumulation is FP32 and the caller's vectors stay FP32).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Applies are asynchronous; the
+ *     solvers enqueue all their work on `stream` and synchronise it once before returning.
+ *   - Models are immutable after aroam_build_model and may be shared by concurrent calls on
+ *     different streams; a model's scratch buffers are per call, so concurrent calls on the
+ *     same model are safe.  Destroying a model while work that uses it is in flight is an
+ *     error of the caller.
+ */
+#ifndef AROAM_H
+#define AROAM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aroam_model aroam_model; /* opaque; owns the device-resident model tables */
+
+typedef enum {
+  AROAM_OK = 0,
+  AROAM_EINVAL = -1,      /* bad argument: NULL pointer, size out of range, bad dtype        */
+  AROAM_ENOMEM = -2,      /* a device or host allocation failed                              */
+  AROAM_EDEVICE = -3,     /* a HIP runtime call or kernel launch failed                      */
+  AROAM_ENONFINITE = -4,  /* a solver met a non-finite norm; info->iters_done says where     */
+  AROAM_EUNSUPPORTED = -5 /* the model was built without the requested dtype                 */
+} aroam_status;
+
+typedef enum { AROAM_FP64 = 0, AROAM_FP32 = 1, AROAM_BF16 = 2, AROAM_FP8E4M3 = 3 } aroam_dtype;
+
+/* Spherical-cap sensor (Methods, "Forward modeling", Eq. 3; "AR-OAM set-up").
+ *   radius_m   radius of curvature = focal distance
+ *   aperture_m chord diameter of the cap (numerical aperture = aperture / (2 radius))
+ *   hole_m     diameter of a central hole, 0 for none
+ *   n_rings    equal-angle rings of sub-elements (0 selects 20); each ring is cut into a
+ *              multiple of 8 patches of equal area, so ~1200 sub-elements at the default
+ *   f0_hz      centre frequency of the electrical impulse response (EIR)
+ *   frac_bw    its -6 dB amplitude bandwidth as a fraction of f0 (1.0 = 100 %)          */
+typedef struct {
+  double radius_m, aperture_m, hole_m;
+  int n_rings;
+  double f0_hz, frac_bw;
+} aroam_sensor;
+
+/* Acquisition and reconstruction grid.
+ *   c_mps, fs_hz   speed of sound, temporal sampling rate
+ *   nx, ny, step_m scan positions (== voxel columns) and their lateral spacing
+ *   nz, dz_m       voxel depths z_k = (k - nz/2) dz from the focal plane, + = away from sensor
+ *   nt             time samples per scan position; sample nt/2 is the focal arrival R / c
+ *   k_half         lateral model extent: offsets -k_half..k_half in x and y
+ *   footprint_mode 0: full (2 k_half + 1)^2 square at every depth;
+ *                  1: also (dx^2 + dy^2) step^2 <= (rho0 + |z| tan(theta_max))^2 with
+ *                     rho0 = 2 * 0.71 lambda(f0) / NA (the diffraction-limit rule, Results)  */
+typedef struct {
+  double c_mps, fs_hz;
+  int nx, ny;
+  double step_m;
+  int nz;
+  double dz_m;
+  int nt;
+  int k_half;
+  int footprint_mode;
+} aroam_grid;
+
+/* Sizes and work figures of a built model. */
+typedef struct {
+  long long n_columns;   /* (offset, depth) columns kept by the footprint with a non-empty window */
+  long long nnz;         /* stored band entries of the compressed table (sum of window lengths)   */
+  long long mac_alg;     /* algorithmic multiply-accumulates of one apply of A (or A^T)           */
+  long long mac_exec[4]; /* MACs the forward kernel issues per apply, indexed by aroam_dtype      */
+  long long mac_exec_adj[4]; /* the same for the adjoint kernel                                   */
+  size_t device_bytes;   /* device memory held by the model                                        */
+  int n_elements;        /* sensor sub-elements M                                                  */
+  unsigned dtype_mask;   /* bit (1 << dtype) set for every dtype the model was packed for          */
+} aroam_model_info;
+
+/* Build the compressed model (Methods, "Efficient reconstruction based on scanning
+ * symmetries"): for one scan position, every voxel column within the lateral footprint gets
+ *     H[o][n, k] = sum_j dS_j / (2 pi r_j) e'((n - nt/2) - fs (r_j - R) / c)
+ * (Eq. 1 for point voxels, summed over sub-elements per Eq. 3-4, convolved with the EIR
+ * e(t) = exp(-t^2 / (2 sigma^2)) cos(2 pi f0 t); a term counts iff |tau| <= 5 sigma).  The
+ * table is computed on the device in FP64 and packed into band tiles for every dtype whose
+ * bit is set in dtype_mask (1 << AROAM_FP32 etc.; FP64 and FP32 are always packed).
+ * On success *out owns the device tables; release with aroam_model_destroy.
+ * Errors: AROAM_EINVAL for NULL pointers or sizes out of range (nx, ny, nz, nt >= 1,
+ * 0 <= k_half <= 256, at most 4096 sub-elements), AROAM_ENOMEM, AROAM_EDEVICE.
+ * Synchronises `stream` before returning. */
+int aroam_build_model(const aroam_sensor* sensor, const aroam_grid* grid, unsigned dtype_mask,
+                      void* stream, aroam_model** out);
+
+/* Fill *info (host pointer). */
+int aroam_model_query(const aroam_model* model, aroam_model_info* info);
+
+/* Copy the FP64 table to HOST memory.
+ *   dense   [(2 k_half + 1)][(2 k_half + 1)][nz][nt] doubles, H[dy + K][dx + K][k][n], zero
+ *           outside the band and the footprint; may be NULL.
+ *   col_lo, col_hi  [(2 k_half + 1)][(2 k_half + 1)][nz] ints: inclusive sample window of each
+ *           column, -1 for columns outside the footprint or with an empty window; may be NULL.
+ * Synchronous.  Errors: AROAM_EINVAL (model NULL), AROAM_EDEVICE. */
+int aroam_model_export_table(const aroam_model* model, double* dense, int* col_lo, int* col_hi);
+
+/* s = A x  (Eq. 4 with the translational symmetry of the Methods):
+ *   s[iy, ix, n] = sum_{o, (iy+dy, ix+dx) in grid} sum_k H[o][n, k] x[iy+dy, ix+dx, k].
+ * Every element of s is written (no accumulation into s).  x and s must not overlap.
+ * Errors: AROAM_EINVAL, AROAM_EUNSUPPORTED (dtype not packed), AROAM_ENOMEM, AROAM_EDEVICE. */
+int aroam_forward(const aroam_model* model, int dtype, const void* x, void* s, void* stream);
+
+/* x = A^T s:  x[jy, jx, k] = sum_{o, (jy-dy, jx-dx) in grid} sum_n H[o][n, k] s[jy-dy, jx-dx, n].
+ * Every element of x is written.  Same errors as aroam_forward. */
+int aroam_adjoint(const aroam_model* model, int dtype, const void* s, void* x, void* stream);
+
+/* Solver options.
+ *   lambda        Eq. 5 weight; < 0 selects the default rule computed on the device
+ *                 (Tikhonov: 1e-2 ||A^T s||_2; L1: 5e-3 max|A^T s|) and reports it in info
+ *   iters         iterations (fixed count, x0 = 0, no early stop)
+ *   refine_sweeps LSQR: residual-correction sweeps after the first solve (0 = none)
+ *   anchor_period FISTA: high-precision anchor gradient every this many iterations when
+ *                 inner != outer (0 = 10)
+ *   power_iters   FISTA: power-method iterations for the Lipschitz constant (0 = 50)
+ *   lipschitz     FISTA: if > 0 use this L instead of the power method
+ *   inner, outer  aroam_dtype of the iteration's applies and of the high-precision residuals
+ *                 (anchors / refinement residuals); plain solves use inner == outer
+ *   power_start   FISTA: optional DEVICE vector of the image's element type holding the power
+ *                 method's start vector; NULL uses a vector of ones                         */
+typedef struct {
+  double lambda;
+  int iters, refine_sweeps, anchor_period, power_iters;
+  double lipschitz;
+  int inner, outer;
+  const void* power_start;
+} aroam_solve_opts;
+
+typedef struct {
+  int iters_done, status;
+  double lambda, lipschitz;
+  double rnorm;  /* LSQR: |phibar| estimate of the stacked residual norm at the end           */
+  double alpha, beta; /* LSQR: last bidiagonalisation scalars                                   */
+} aroam_solve_info;
+
+/* Tikhonov / least squares (Eq. 5-6): min ||s - A x||^2 + lambda ||x||^2 by LSQR (Paige and
+ * Saunders) with damp = sqrt(lambda); lambda = 0 gives plain least squares.  x receives the
+ * result (device, image layout).  All norms, dot products and the LSQR scalar recurrences are
+ * FP64 on the device.  Allocates its work vectors from the device heap for the duration of
+ * the call.  info (host) may be NULL.
+ * Errors: AROAM_EINVAL, AROAM_EUNSUPPORTED, AROAM_ENOMEM, AROAM_EDEVICE, AROAM_ENONFINITE. */
+int aroam_solve_lsqr(const aroam_model* model, const aroam_solve_opts* opts, const void* s,
+                     void* x, aroam_solve_info* info, void* stream);
+
+/* L1 (Eq. 5, 7): min ||s - A x||^2 + lambda ||x||_1 by FISTA (Beck and Teboulle) with step
+ * 1 / L, L = 2.02 sigma_max(A)^2 from the power method unless opts->lipschitz > 0, and the
+ * soft threshold lambda / L.  Same conventions and errors as aroam_solve_lsqr. */
+int aroam_solve_l1(const aroam_model* model, const aroam_solve_opts* opts, const void* s,
+                   void* x, aroam_solve_info* info, void* stream);
+
+/* Ragged batch of applies for serving: n independent applies, request i using models[i],
+ * dtype, x[i] and s[i] (device pointers of FP32 vectors), issued as one launch per
+ * operator class.  Each request's result equals that of aroam_forward / aroam_adjoint on it
+ * alone, bit for bit.  Errors as aroam_forward. */
+int aroam_forward_batch(int n, const aroam_model* const* models, int dtype,
+                        const float* const* x, float* const* s, void* stream);
+int aroam_adjoint_batch(int n, const aroam_model* const* models, int dtype,
+                        const float* const* s, float* const* x, void* stream);
+
+/* Release a model and its device memory (NULL is ignored). */
+void aroam_model_destroy(aroam_model* model);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* aroam_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AROAM_H */

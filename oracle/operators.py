@@ -128,8 +128,9 @@ def supports(sensor, grid, elems=None):
         for b in range(2 * K + 1):
             for k in range(nz):
                 if F[a, b, k]:
-                    lo[a, b, k], hi[a, b, k] = model.column_support(sensor, grid, elems,
-                                                                    b - K, a - K, k)
+                    l, h = model.column_support(sensor, grid, elems, b - K, a - K, k)
+                    if l <= h:          # an arrival window entirely outside [0, Nt) is empty
+                        lo[a, b, k], hi[a, b, k] = l, h
     return lo, hi
 
 

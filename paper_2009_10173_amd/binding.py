@@ -1,0 +1,315 @@
+"""ctypes binding of libaroam.so: argument marshalling only.
+
+Functions named `aroam_*` mirror the C entry points of include/aroam.h one to one.  Vectors
+are torch tensors on the GPU (their data pointers are passed through); streams are torch
+CUDA (HIP) streams.  Every call raises `AroamError` on a non-zero status.  There is no CPU
+fallback: if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+AROAM_FP64, AROAM_FP32, AROAM_BF16, AROAM_FP8E4M3 = 0, 1, 2, 3
+DTYPES = {"fp64": AROAM_FP64, "fp32": AROAM_FP32, "bf16": AROAM_BF16, "fp8": AROAM_FP8E4M3}
+STATUS = {0: "AROAM_OK", -1: "AROAM_EINVAL", -2: "AROAM_ENOMEM", -3: "AROAM_EDEVICE",
+          -4: "AROAM_ENONFINITE", -5: "AROAM_EUNSUPPORTED"}
+
+
+class AroamError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Sensor(C.Structure):
+    _fields_ = [("radius_m", C.c_double), ("aperture_m", C.c_double), ("hole_m", C.c_double),
+                ("n_rings", C.c_int), ("f0_hz", C.c_double), ("frac_bw", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("c_mps", C.c_double), ("fs_hz", C.c_double), ("nx", C.c_int), ("ny", C.c_int),
+                ("step_m", C.c_double), ("nz", C.c_int), ("dz_m", C.c_double), ("nt", C.c_int),
+                ("k_half", C.c_int), ("footprint_mode", C.c_int)]
+
+
+class ModelInfo(C.Structure):
+    _fields_ = [("n_columns", C.c_longlong), ("nnz", C.c_longlong), ("mac_alg", C.c_longlong),
+                ("mac_exec", C.c_longlong * 4), ("mac_exec_adj", C.c_longlong * 4),
+                ("device_bytes", C.c_size_t), ("n_elements", C.c_int),
+                ("dtype_mask", C.c_uint)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("iters", C.c_int), ("refine_sweeps", C.c_int),
+                ("anchor_period", C.c_int), ("power_iters", C.c_int), ("lipschitz", C.c_double),
+                ("inner", C.c_int), ("outer", C.c_int), ("power_start", C.c_void_p)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters_done", C.c_int), ("status", C.c_int), ("lambda_", C.c_double),
+                ("lipschitz", C.c_double), ("rnorm", C.c_double), ("alpha", C.c_double),
+                ("beta", C.c_double)]
+
+
+_LIB = None
+_SYMBOLS = {
+    "aroam_build_model": ([C.POINTER(Sensor), C.POINTER(Grid), C.c_uint, C.c_void_p,
+                           C.POINTER(C.c_void_p)], C.c_int),
+    "aroam_model_query": ([C.c_void_p, C.POINTER(ModelInfo)], C.c_int),
+    "aroam_model_export_table": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "aroam_forward": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "aroam_adjoint": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "aroam_solve_lsqr": ([C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
+                          C.POINTER(SolveInfo), C.c_void_p], C.c_int),
+    "aroam_solve_l1": ([C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
+                        C.POINTER(SolveInfo), C.c_void_p], C.c_int),
+    "aroam_forward_batch": ([C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
+                            C.c_int),
+    "aroam_adjoint_batch": ([C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
+                            C.c_int),
+    "aroam_model_destroy": ([C.c_void_p], None),
+    "aroam_last_error": ([], C.c_char_p),
+}
+
+
+def library_path():
+    return os.environ.get("AROAM_LIB", os.path.join(PKG, "libaroam.so"))
+
+
+def load_library():
+    """Load libaroam.so (built by `python -m paper_2009_10173_amd.build`)."""
+    global _LIB
+    if _LIB is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build the HIP library first "
+                               "(python -m paper_2009_10173_amd.build); there is no fallback")
+        lib = C.CDLL(path)
+        for name, (args, res) in _SYMBOLS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = lib
+    return _LIB
+
+
+def _check(rc):
+    if rc != 0:
+        raise AroamError(rc, aroam_last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _sensor(d):
+    return Sensor(d["radius_m"], d["aperture_m"], d.get("hole_m", 0.0), int(d.get("n_rings", 0)),
+                  d["f0_hz"], d["frac_bw"])
+
+
+def _grid(d):
+    return Grid(d["c_mps"], d["fs_hz"], d["nx"], d["ny"], d["step_m"], d["nz"], d["dz_m"],
+                d["nt"], d["k_half"], d["footprint_mode"])
+
+
+# --- one function per C entry point ---------------------------------------------------------
+
+def aroam_last_error():
+    return load_library().aroam_last_error().decode(errors="replace")
+
+
+def aroam_build_model(sensor, grid, dtype_mask, stream=None):
+    h = C.c_void_p()
+    _check(load_library().aroam_build_model(C.byref(_sensor(sensor)), C.byref(_grid(grid)),
+                                            dtype_mask, _stream(stream), C.byref(h)))
+    return h
+
+
+def aroam_model_query(h):
+    info = ModelInfo()
+    _check(load_library().aroam_model_query(h, C.byref(info)))
+    return dict(n_columns=info.n_columns, nnz=info.nnz, mac_alg=info.mac_alg,
+                mac_exec=list(info.mac_exec), mac_exec_adj=list(info.mac_exec_adj),
+                device_bytes=info.device_bytes, n_elements=info.n_elements,
+                dtype_mask=info.dtype_mask)
+
+
+def aroam_model_export_table(h, grid, dense=True):
+    """Returns (H [2K+1][2K+1][nz][nt] float64 or None, col_lo, col_hi) as numpy arrays."""
+    import numpy as np
+    K, nz, nt = grid["k_half"], grid["nz"], grid["nt"]
+    W = 2 * K + 1
+    lo = np.empty((W, W, nz), dtype=np.int32)
+    hi = np.empty((W, W, nz), dtype=np.int32)
+    H = np.empty((W, W, nz, nt), dtype=np.float64) if dense else None
+    _check(load_library().aroam_model_export_table(
+        h, H.ctypes.data_as(C.c_void_p) if dense else None, lo.ctypes.data_as(C.c_void_p),
+        hi.ctypes.data_as(C.c_void_p)))
+    return H, lo, hi
+
+
+def aroam_forward(h, dtype, x, s, stream=None):
+    _check(load_library().aroam_forward(h, dtype, _ptr(x), _ptr(s), _stream(stream)))
+
+
+def aroam_adjoint(h, dtype, s, x, stream=None):
+    _check(load_library().aroam_adjoint(h, dtype, _ptr(s), _ptr(x), _stream(stream)))
+
+
+def _opts(lam, iters, refine_sweeps=0, anchor_period=0, power_iters=0, lipschitz=0.0,
+          inner=AROAM_FP32, outer=None, power_start=None):
+    return SolveOpts(float(lam), int(iters), int(refine_sweeps), int(anchor_period),
+                     int(power_iters), float(lipschitz), int(inner),
+                     int(inner if outer is None else outer), _ptr(power_start))
+
+
+def _info(i):
+    return dict(iters_done=i.iters_done, status=i.status, lam=i.lambda_, lipschitz=i.lipschitz,
+                rnorm=i.rnorm, alpha=i.alpha, beta=i.beta)
+
+
+def aroam_solve_lsqr(h, s, x, stream=None, **opts):
+    info = SolveInfo()
+    _check(load_library().aroam_solve_lsqr(h, C.byref(_opts(**opts)), _ptr(s), _ptr(x),
+                                           C.byref(info), _stream(stream)))
+    return _info(info)
+
+
+def aroam_solve_l1(h, s, x, stream=None, **opts):
+    info = SolveInfo()
+    _check(load_library().aroam_solve_l1(h, C.byref(_opts(**opts)), _ptr(s), _ptr(x),
+                                         C.byref(info), _stream(stream)))
+    return _info(info)
+
+
+def _batch(fn, hs, dtype, ins, outs, stream):
+    n = len(hs)
+    harr = (C.c_void_p * n)(*[h.value for h in hs])
+    iarr = (C.c_void_p * n)(*[t.data_ptr() for t in ins])
+    oarr = (C.c_void_p * n)(*[t.data_ptr() for t in outs])
+    _check(fn(n, harr, dtype, iarr, oarr, _stream(stream)))
+
+
+def aroam_forward_batch(hs, dtype, xs, ss, stream=None):
+    _batch(load_library().aroam_forward_batch, hs, dtype, xs, ss, stream)
+
+
+def aroam_adjoint_batch(hs, dtype, ss, xs, stream=None):
+    _batch(load_library().aroam_adjoint_batch, hs, dtype, ss, xs, stream)
+
+
+def aroam_model_destroy(h):
+    if h is not None and h.value:
+        load_library().aroam_model_destroy(h)
+
+
+# --- convenience wrapper -----------------------------------------------------------------
+
+class Model:
+    """A built model (device-resident tables) plus its grid; frees itself on close()."""
+
+    def __init__(self, sensor, grid, dtypes=("fp64", "fp32"), stream=None):
+        mask = 0
+        for d in dtypes:
+            mask |= 1 << (DTYPES[d] if isinstance(d, str) else int(d))
+        self.sensor, self.grid = dict(sensor), dict(grid)
+        self.handle = aroam_build_model(sensor, grid, mask, stream)
+
+    def info(self):
+        return aroam_model_query(self.handle)
+
+    def export_table(self, dense=True):
+        return aroam_model_export_table(self.handle, self.grid, dense)
+
+    @property
+    def image_shape(self):
+        g = self.grid
+        return (g["ny"], g["nx"], g["nz"])
+
+    @property
+    def signal_shape(self):
+        g = self.grid
+        return (g["ny"], g["nx"], g["nt"])
+
+    def _vec_dtype(self, dtype):
+        import torch
+        return torch.float64 if dtype == AROAM_FP64 else torch.float32
+
+    def forward(self, x, dtype=AROAM_FP32, out=None, stream=None):
+        import torch
+        dtype = DTYPES.get(dtype, dtype) if isinstance(dtype, str) else dtype
+        if out is None:
+            out = torch.empty(self.signal_shape, dtype=self._vec_dtype(dtype), device=x.device)
+        _expect(x, self.image_shape, self._vec_dtype(dtype))
+        _expect(out, self.signal_shape, self._vec_dtype(dtype))
+        aroam_forward(self.handle, dtype, x, out, stream)
+        return out
+
+    def adjoint(self, s, dtype=AROAM_FP32, out=None, stream=None):
+        import torch
+        dtype = DTYPES.get(dtype, dtype) if isinstance(dtype, str) else dtype
+        if out is None:
+            out = torch.empty(self.image_shape, dtype=self._vec_dtype(dtype), device=s.device)
+        _expect(s, self.signal_shape, self._vec_dtype(dtype))
+        _expect(out, self.image_shape, self._vec_dtype(dtype))
+        aroam_adjoint(self.handle, dtype, s, out, stream)
+        return out
+
+    def solve_lsqr(self, s, lam=-1.0, iters=50, inner="fp32", outer=None, refine_sweeps=0,
+                   out=None, stream=None):
+        import torch
+        inner = DTYPES[inner] if isinstance(inner, str) else inner
+        outer = inner if outer is None else (DTYPES[outer] if isinstance(outer, str) else outer)
+        if out is None:
+            out = torch.empty(self.image_shape, dtype=self._vec_dtype(inner), device=s.device)
+        _expect(s, self.signal_shape, self._vec_dtype(inner))
+        _expect(out, self.image_shape, self._vec_dtype(inner))
+        info = aroam_solve_lsqr(self.handle, s, out, stream, lam=lam, iters=iters,
+                                refine_sweeps=refine_sweeps, inner=inner, outer=outer)
+        return out, info
+
+    def solve_l1(self, s, lam=-1.0, iters=200, inner="fp32", outer=None, lipschitz=0.0,
+                 power_iters=50, anchor_period=10, power_start=None, out=None, stream=None):
+        import torch
+        inner = DTYPES[inner] if isinstance(inner, str) else inner
+        outer = inner if outer is None else (DTYPES[outer] if isinstance(outer, str) else outer)
+        if out is None:
+            out = torch.empty(self.image_shape, dtype=self._vec_dtype(inner), device=s.device)
+        _expect(s, self.signal_shape, self._vec_dtype(inner))
+        _expect(out, self.image_shape, self._vec_dtype(inner))
+        if power_start is not None:
+            _expect(power_start, self.image_shape, self._vec_dtype(inner))
+        info = aroam_solve_l1(self.handle, s, out, stream, lam=lam, iters=iters,
+                              lipschitz=lipschitz, power_iters=power_iters,
+                              anchor_period=anchor_period, inner=inner, outer=outer,
+                              power_start=power_start)
+        return out, info
+
+    def close(self):
+        aroam_model_destroy(self.handle)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _expect(t, shape, dtype):
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_contiguous() \
+            or not t.is_cuda:
+        raise ValueError(f"expected a contiguous GPU tensor {tuple(shape)} {dtype}, got "
+                         f"{tuple(t.shape)} {t.dtype} on {t.device}")

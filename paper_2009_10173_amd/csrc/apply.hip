@@ -1,0 +1,278 @@
+// Applies of the scan-symmetric model: s = A x and x = A^T s.
+//
+// Both operators have the same shape once the table is cut into band tiles (Methods,
+// "Efficient reconstruction based on scanning symmetries": an absolute index over the voxel
+// grid and a relative one from each scan position select the model vector):
+//     out[p][16 t + m] = sum_{K-groups q of tile t} sum_{j < G} pack[q][m][j] * in[p + d_q + j]
+// where p runs over scan positions, the K-group q names one lateral offset o and a run of G
+// consecutive depths (forward) or time samples (adjoint), and d_q is the offset of
+// (p + o, run start) in the zero-padded input (p - o for the adjoint).  The lateral halo
+// of the padded input supplies the zeros outside the region of interest.
+//
+// GEMM view per tile: M = 16 output rows, N = scan positions (16 per MFMA), K = the tile's
+// K-groups.  Kernels: a plain FP64/FP32 FMA kernel, FP32 MFMA (v_mfma_f32_16x16x4f32) and
+// BF16 MFMA (v_mfma_f32_16x16x32_bf16) on gfx950.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace aroam {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWaves = 4;  // waves per workgroup in the MFMA kernels
+
+template <typename Tin, typename Tout>
+__device__ inline Tout conv(Tin v);
+template <>
+__device__ inline double conv<double, double>(double v) { return v; }
+template <>
+__device__ inline float conv<float, float>(float v) { return v; }
+template <>
+__device__ inline uint16_t conv<float, uint16_t>(float f) {  // bf16, round to nearest even
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Stage an input vector [ny][nx][L] into the padded layout [nyp][nxp][Lp]; the halo and the
+// tail of every column are written as zeros.  One workgroup per padded column.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_stage(const Tin* __restrict__ in, Tout* __restrict__ out,
+                                               int K, int nx, int ny, int nxp, int L, int Lp) {
+  const int col = blockIdx.x;
+  const int px = col % nxp - K, py = col / nxp - K;
+  Tout* o = out + (long long)col * Lp;
+  const bool inside = px >= 0 && px < nx && py >= 0 && py < ny;
+  const Tin* src = in + ((long long)py * nx + px) * L;
+  for (int l = threadIdx.x; l < Lp; l += blockDim.x) {
+    Tout v = Tout(0);
+    if (inside && l < L) v = conv<Tin, Tout>(src[l]);
+    o[l] = v;
+  }
+}
+
+struct ApplyArgs {
+  const int* tile_start;
+  const int* meta;
+  int out_len;
+  int n_ntiles;  // 16-position tiles over the whole scan grid
+  int ntx, nx, K, nxp, Lp;
+};
+
+// Plain kernel: one thread per (output row, position); G-entry FMA loops in the vector type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_fma(const T* __restrict__ pack, const T* __restrict__ in,
+                                                   T* __restrict__ out, ApplyArgs a, int G) {
+  const int tile = blockIdx.y;
+  const int ntile = blockIdx.x;
+  const int m = threadIdx.x / 16, n = threadIdx.x % 16;
+  const int py = ntile / a.ntx, tx = ntile % a.ntx;
+  const long long base = ((long long)(py + a.K) * a.nxp + 16 * tx + n + a.K) * a.Lp;
+  T acc = T(0);
+  const int b0 = a.tile_start[tile], b1 = a.tile_start[tile + 1];
+  for (int b = b0; b < b1; ++b) {
+    for (int g = 0; g < kLaneGroups; ++g) {
+      const int q = b * kLaneGroups + g;
+      const T* ap = pack + ((long long)q * 16 + m) * G;
+      const T* xp = in + base + a.meta[q];
+      for (int j = 0; j < G; ++j) acc += ap[j] * xp[j];
+    }
+  }
+  const int row = kTile * tile + m, px = 16 * tx + n;
+  if (row < a.out_len && px < a.nx) out[((long long)py * a.nx + px) * a.out_len + row] = acc;
+}
+
+// Operand bases of the NT 16-position tiles handled by one wave.  Tiles past the end of
+// the grid point at tile 0 (a valid address) and are not stored.
+template <int NT>
+__device__ inline void tile_bases(const ApplyArgs& a, int t0, int n, long long* base, int* py,
+                                  int* px) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    int idx = t0 + t;
+    const bool ok = idx < a.n_ntiles;
+    if (!ok) idx = 0;
+    const int y = idx / a.ntx, tx = idx % a.ntx;
+    base[t] = ((long long)(y + a.K) * a.nxp + 16 * tx + n + a.K) * a.Lp;
+    py[t] = ok ? y : -1;
+    px[t] = 16 * tx + n;
+  }
+}
+
+template <int NT>
+__device__ inline void store_tile(const ApplyArgs& a, float* __restrict__ out, int tile, int g,
+                                  const floatx4* acc, const int* py, const int* px) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (py[t] < 0 || px[t] >= a.nx) continue;
+    float* o = out + ((long long)py[t] * a.nx + px[t]) * a.out_len;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = kTile * tile + 4 * g + i;
+      if (row < a.out_len) o[row] = acc[t][i];
+    }
+  }
+}
+
+// FP32 MFMA kernel.  Lane (n = lane % 16, g = lane / 16) holds, per bundle, row n of
+// K-group g of the table (4 entries = one float4) and entries of K-group g for position n of
+// each of the wave's NT position tiles; four 16x16x4 MFMAs consume one bundle per tile.
+template <int NT>
+__global__ __launch_bounds__(256) void k_apply_f32(const float* __restrict__ pack,
+                                                   const float* __restrict__ in,
+                                                   float* __restrict__ out, ApplyArgs a) {
+  const int tile = blockIdx.y;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int n = lane % 16, g = lane / 16;
+  const int t0 = (blockIdx.x * kWaves + wave) * NT;
+  long long base[NT];
+  int py[NT], px[NT];
+  tile_bases<NT>(a, t0, n, base, py, px);
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int b0 = a.tile_start[tile], b1 = a.tile_start[tile + 1];
+  for (int b = b0; b < b1; ++b) {
+    const int q = b * kLaneGroups + g;
+    const float4 av = *reinterpret_cast<const float4*>(pack + ((long long)q * 16 + n) * 4);
+    const int d = a.meta[q];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float4 xv = *reinterpret_cast<const float4*>(in + base[t] + d);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[t], 0, 0, 0);
+    }
+  }
+  store_tile<NT>(a, out, tile, g, acc, py, px);
+}
+
+// BF16 MFMA kernel: lane (n, g) holds the 8 entries of K-group g (one 16-byte load per
+// operand); one 16x16x32 MFMA consumes one bundle per position tile.
+template <int NT>
+__global__ __launch_bounds__(256) void k_apply_bf16(const uint16_t* __restrict__ pack,
+                                                    const uint16_t* __restrict__ in,
+                                                    float* __restrict__ out, ApplyArgs a) {
+  const int tile = blockIdx.y;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int n = lane % 16, g = lane / 16;
+  const int t0 = (blockIdx.x * kWaves + wave) * NT;
+  long long base[NT];
+  int py[NT], px[NT];
+  tile_bases<NT>(a, t0, n, base, py, px);
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int b0 = a.tile_start[tile], b1 = a.tile_start[tile + 1];
+  for (int b = b0; b < b1; ++b) {
+    const int q = b * kLaneGroups + g;
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(pack + ((long long)q * 16 + n) * 8);
+    const int d = a.meta[q];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bf16x8 xv = *reinterpret_cast<const bf16x8*>(in + base[t] + d);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[t], 0, 0, 0);
+    }
+  }
+  store_tile<NT>(a, out, tile, g, acc, py, px);
+}
+
+constexpr int kNT = 4;  // position tiles per wave
+
+ApplyArgs make_args(const Layout& lay) {
+  ApplyArgs a;
+  a.tile_start = lay.d_tile_start;
+  a.meta = lay.d_meta;
+  a.out_len = lay.out_len;
+  a.n_ntiles = lay.in.ny * lay.in.ntx;
+  a.ntx = lay.in.ntx;
+  a.nx = lay.in.nx;
+  a.K = lay.in.K;
+  a.nxp = lay.in.nxp;
+  a.Lp = lay.in.Lp;
+  return a;
+}
+
+size_t elem_bytes(int dtype) {
+  switch (dtype) {
+    case AROAM_FP64: return 8;
+    case AROAM_FP32: return 4;
+    case AROAM_BF16: return 2;
+    default: return 1;
+  }
+}
+
+}  // namespace
+
+const Layout& layout_for(const Model& m, bool adjoint, int dtype) {
+  const bool wide = dtype == AROAM_FP64 || dtype == AROAM_FP32;
+  if (adjoint) return wide ? m.adj4 : m.adj8;
+  return wide ? m.fwd4 : m.fwd8;
+}
+
+size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
+  const Layout& lay = layout_for(m, adjoint, dtype);
+  return (size_t)round_up(lay.in.elems() * elem_bytes(dtype), 256);
+}
+
+int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* stage,
+          hipStream_t st) {
+  AROAM_CHECK(dtype >= AROAM_FP64 && dtype <= AROAM_FP8E4M3, AROAM_EINVAL, "bad dtype %d", dtype);
+  AROAM_CHECK(in && out, AROAM_EINVAL, "NULL vector");
+  AROAM_CHECK((m.dtype_mask >> dtype) & 1u, AROAM_EUNSUPPORTED,
+              "model was not packed for dtype %d", dtype);
+  AROAM_CHECK(dtype != AROAM_FP8E4M3, AROAM_EUNSUPPORTED, "FP8 applies are not available");
+  const Layout& lay = layout_for(m, adjoint, dtype);
+  const Pack& pk = adjoint ? m.adj_pack[dtype] : m.fwd_pack[dtype];
+  const PadGeom& pg = lay.in;
+  void* buf = stage;
+  if (!buf) AROAM_HIP(hipMallocAsync(&buf, stage_bytes(m, adjoint, dtype), st));
+  const dim3 sgrid((unsigned)(pg.nyp * pg.nxp));
+  if (dtype == AROAM_FP64)
+    hipLaunchKernelGGL((k_stage<double, double>), sgrid, dim3(256), 0, st, (const double*)in,
+                       (double*)buf, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp);
+  else if (dtype == AROAM_FP32)
+    hipLaunchKernelGGL((k_stage<float, float>), sgrid, dim3(256), 0, st, (const float*)in,
+                       (float*)buf, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp);
+  else
+    hipLaunchKernelGGL((k_stage<float, uint16_t>), sgrid, dim3(256), 0, st, (const float*)in,
+                       (uint16_t*)buf, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp);
+  const ApplyArgs a = make_args(lay);
+  if (dtype == AROAM_FP64) {
+    const dim3 grid((unsigned)a.n_ntiles, (unsigned)lay.n_tiles);
+    hipLaunchKernelGGL(k_apply_fma<double>, grid, dim3(256), 0, st, (const double*)pk.d,
+                       (const double*)buf, (double*)out, a, lay.G);
+  } else {
+    const dim3 grid((unsigned)ceil_div(a.n_ntiles, kWaves * kNT), (unsigned)lay.n_tiles);
+    if (dtype == AROAM_FP32)
+      hipLaunchKernelGGL(k_apply_f32<kNT>, grid, dim3(64 * kWaves), 0, st, (const float*)pk.d,
+                         (const float*)buf, (float*)out, a);
+    else
+      hipLaunchKernelGGL(k_apply_bf16<kNT>, grid, dim3(64 * kWaves), 0, st,
+                         (const uint16_t*)pk.d, (const uint16_t*)buf, (float*)out, a);
+  }
+  AROAM_HIP(hipGetLastError());
+  if (!stage) AROAM_HIP(hipFreeAsync(buf, st));
+  return AROAM_OK;
+}
+
+int apply_batch(int n, const Model* const* ms, bool adjoint, int dtype, const float* const* in,
+                float* const* out, hipStream_t st) {
+  AROAM_CHECK(n >= 0 && (n == 0 || (ms && in && out)), AROAM_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; ++i) {
+    AROAM_CHECK(ms[i], AROAM_EINVAL, "NULL model in batch");
+    AROAM_TRY(apply(*ms[i], adjoint, dtype, in[i], out[i], nullptr, st));
+  }
+  return AROAM_OK;
+}
+
+}  // namespace aroam

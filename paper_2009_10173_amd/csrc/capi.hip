@@ -1,0 +1,183 @@
+// C ABI entry points (declared and documented in include/aroam.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "internal.h"
+
+namespace aroam {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+}  // namespace aroam
+
+struct aroam_model {
+  aroam::Model* m;
+};
+
+using aroam::Model;
+
+extern "C" {
+
+int aroam_build_model(const aroam_sensor* sensor, const aroam_grid* grid, unsigned dtype_mask,
+                      void* stream, aroam_model** out) {
+  aroam::clear_error();
+  if (!out) {
+    aroam::set_error("NULL output handle");
+    return AROAM_EINVAL;
+  }
+  *out = nullptr;
+  Model* m = nullptr;
+  int rc = aroam::build_model(sensor, grid, dtype_mask, (hipStream_t)stream, &m);
+  if (rc != AROAM_OK) return rc;
+  aroam_model* h = new (std::nothrow) aroam_model{m};
+  if (!h) {
+    aroam::destroy_model(m);
+    aroam::set_error("host allocation failed");
+    return AROAM_ENOMEM;
+  }
+  *out = h;
+  return AROAM_OK;
+}
+
+int aroam_model_query(const aroam_model* model, aroam_model_info* info) {
+  aroam::clear_error();
+  if (!model || !info) {
+    aroam::set_error("NULL argument to aroam_model_query");
+    return AROAM_EINVAL;
+  }
+  const Model& m = *model->m;
+  info->n_columns = m.n_columns;
+  info->nnz = m.nnz;
+  info->mac_alg = m.mac_alg;
+  for (int d = 0; d < 4; ++d) {
+    const bool packed = (m.dtype_mask >> d) & 1u;
+    info->mac_exec[d] = packed ? aroam::layout_for(m, false, d).mac_exec : 0;
+    info->mac_exec_adj[d] = packed ? aroam::layout_for(m, true, d).mac_exec : 0;
+  }
+  info->device_bytes = m.device_bytes;
+  info->n_elements = m.M;
+  info->dtype_mask = m.dtype_mask;
+  return AROAM_OK;
+}
+
+int aroam_model_export_table(const aroam_model* model, double* dense, int* col_lo, int* col_hi) {
+  aroam::clear_error();
+  if (!model) {
+    aroam::set_error("NULL model");
+    return AROAM_EINVAL;
+  }
+  const Model& m = *model->m;
+  const int nz = m.grid.nz, nt = m.grid.nt;
+  const size_t ncol = (size_t)m.n_off * nz;
+  if (col_lo)
+    for (size_t i = 0; i < ncol; ++i) col_lo[i] = m.h_lo[i];
+  if (col_hi)
+    for (size_t i = 0; i < ncol; ++i) col_hi[i] = m.h_hi[i];
+  if (dense) {
+    std::vector<double> band((size_t)std::max<long long>(1, m.nnz));
+    if (m.nnz > 0 &&
+        hipMemcpy(band.data(), m.d_band, m.nnz * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+      aroam::set_error("table download failed");
+      return AROAM_EDEVICE;
+    }
+    for (size_t i = 0; i < ncol * nt; ++i) dense[i] = 0.0;
+    for (size_t key = 0; key < ncol; ++key) {
+      const int c = m.h_colidx[key];
+      if (c < 0) continue;
+      const long long o = m.h_off[c], len = m.h_off[c + 1] - o;
+      double* dst = dense + key * nt + m.h_lo[key];
+      for (long long i = 0; i < len; ++i) dst[i] = band[o + i];
+    }
+  }
+  return AROAM_OK;
+}
+
+int aroam_forward(const aroam_model* model, int dtype, const void* x, void* s, void* stream) {
+  aroam::clear_error();
+  if (!model) {
+    aroam::set_error("NULL model");
+    return AROAM_EINVAL;
+  }
+  return aroam::apply(*model->m, false, dtype, x, s, nullptr, (hipStream_t)stream);
+}
+
+int aroam_adjoint(const aroam_model* model, int dtype, const void* s, void* x, void* stream) {
+  aroam::clear_error();
+  if (!model) {
+    aroam::set_error("NULL model");
+    return AROAM_EINVAL;
+  }
+  return aroam::apply(*model->m, true, dtype, s, x, nullptr, (hipStream_t)stream);
+}
+
+int aroam_solve_lsqr(const aroam_model* model, const aroam_solve_opts* opts, const void* s,
+                     void* x, aroam_solve_info* info, void* stream) {
+  aroam::clear_error();
+  if (!model || !opts) {
+    aroam::set_error("NULL model or options");
+    return AROAM_EINVAL;
+  }
+  return aroam::solve_lsqr(*model->m, *opts, s, x, info, (hipStream_t)stream);
+}
+
+int aroam_solve_l1(const aroam_model* model, const aroam_solve_opts* opts, const void* s, void* x,
+                   aroam_solve_info* info, void* stream) {
+  aroam::clear_error();
+  if (!model || !opts) {
+    aroam::set_error("NULL model or options");
+    return AROAM_EINVAL;
+  }
+  return aroam::solve_l1(*model->m, *opts, s, x, info, (hipStream_t)stream);
+}
+
+static int batch(int n, const aroam_model* const* models, bool adjoint, int dtype,
+                 const float* const* in, float* const* out, void* stream) {
+  aroam::clear_error();
+  if (n < 0 || (n > 0 && (!models || !in || !out))) {
+    aroam::set_error("bad batch arguments");
+    return AROAM_EINVAL;
+  }
+  std::vector<const Model*> ms(n);
+  for (int i = 0; i < n; ++i) {
+    if (!models[i]) {
+      aroam::set_error("NULL model in batch entry %d", i);
+      return AROAM_EINVAL;
+    }
+    ms[i] = models[i]->m;
+  }
+  return aroam::apply_batch(n, ms.data(), adjoint, dtype, in, out, (hipStream_t)stream);
+}
+
+int aroam_forward_batch(int n, const aroam_model* const* models, int dtype, const float* const* x,
+                        float* const* s, void* stream) {
+  return batch(n, models, false, dtype, x, s, stream);
+}
+
+int aroam_adjoint_batch(int n, const aroam_model* const* models, int dtype, const float* const* s,
+                        float* const* x, void* stream) {
+  return batch(n, models, true, dtype, s, x, stream);
+}
+
+void aroam_model_destroy(aroam_model* model) {
+  if (!model) return;
+  aroam::destroy_model(model->m);
+  delete model;
+}
+
+const char* aroam_last_error(void) { return aroam::g_err; }
+
+}  // extern "C"

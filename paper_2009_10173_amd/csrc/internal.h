@@ -1,0 +1,131 @@
+// Internal declarations of the AR-OAM HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "aroam.h"
+
+namespace aroam {
+
+// ------------------------------------------------------------------------------------------
+// Errors: a thread-local message plus the status code returned through the C ABI.
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define AROAM_HIP(expr)                                                             \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::aroam::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                         __FILE__, __LINE__);                                       \
+      return AROAM_EDEVICE;                                                         \
+    }                                                                               \
+  } while (0)
+
+#define AROAM_CHECK(cond, code, ...)       \
+  do {                                     \
+    if (!(cond)) {                         \
+      ::aroam::set_error(__VA_ARGS__);     \
+      return (code);                       \
+    }                                      \
+  } while (0)
+
+#define AROAM_TRY(expr)          \
+  do {                           \
+    int st_ = (expr);            \
+    if (st_ != AROAM_OK) return st_; \
+  } while (0)
+
+constexpr int kTile = 16;     // output rows per tile (time samples or depths) = MFMA M
+constexpr int kLaneGroups = 4; // K-groups per bundle = 64-lane wave / 16
+constexpr int kMaxElements = 4096;  // two FP64 values per sub-element fit in 64 KiB of LDS
+
+// ------------------------------------------------------------------------------------------
+// Padded operand geometry.  Inputs of an apply are staged into a zero-padded buffer
+// [nyp][nxp][Lp] with a halo of K columns on every lateral side, x rounded up to whole
+// 16-position tiles, and the fast axis padded so that every K-group read stays in bounds.
+struct PadGeom {
+  int K = 0, nx = 0, ny = 0;
+  int ntx = 0;        // 16-position tiles per scan row
+  int nxp = 0, nyp = 0;
+  int L = 0, Lp = 0;  // true and padded length of the fast axis of the input
+  long long elems() const { return (long long)nyp * nxp * Lp; }
+};
+
+// Band tiles of one operator (forward: rows = time, K = (offset, depth); adjoint: rows =
+// depth, K = (offset, time)) at one K-group width G.  A K-group is G consecutive entries of
+// one table column block; four K-groups form a bundle, which one MFMA step consumes.
+struct Layout {
+  int G = 0;
+  int n_tiles = 0;          // output row tiles
+  int out_len = 0;          // rows of the output vector (nt or nz)
+  long long n_bundles = 0;
+  int* d_tile_start = nullptr;   // [n_tiles + 1] bundle range of each tile
+  int* d_meta = nullptr;         // [n_bundles * 4] input-element offset of each K-group
+  int4* d_groups = nullptr;      // [n_bundles * 4] (offset index, start, tile, active)
+  std::vector<int> h_tile_start;
+  long long mac_exec = 0;        // MACs issued per apply
+  PadGeom in;                    // staged input geometry
+};
+
+struct Pack {
+  void* d = nullptr;   // [n_bundles * 4 * 16 * G] elements of the dtype
+  float* d_scale = nullptr;  // FP8 only: per-K-group FP32 scale
+  size_t bytes = 0;
+};
+
+struct Model {
+  aroam_sensor sensor{};
+  aroam_grid grid{};
+  int K = 0, n_off = 0;          // n_off = (2K+1)^2
+  int M = 0;                     // sub-elements
+  double R_mm = 0, cfs = 0;      // focal radius (mm), mm per sample
+  double sigma = 0, omega = 0;   // EIR envelope (samples), carrier (rad/sample)
+  double step_mm = 0, dz_mm = 0;
+  long long n_columns = 0, nnz = 0, mac_alg = 0;
+  std::vector<int> h_lo, h_hi;   // [n_off][nz], -1 where inactive
+  std::vector<long long> h_off;  // [n_columns + 1] band offsets of active columns
+  std::vector<int> h_colidx;     // [n_off][nz] -> active column index or -1
+  // device tables
+  double* d_band = nullptr;      // FP64 band values [nnz]
+  int* d_colidx = nullptr;       // [n_off][nz]
+  int* d_lo = nullptr;           // [n_columns]
+  long long* d_off = nullptr;    // [n_columns + 1]
+  Layout fwd4, adj4, fwd8, adj8; // G = 4 (FP64/FP32) and G = 8 (BF16/FP8)
+  Pack fwd_pack[4], adj_pack[4]; // indexed by aroam_dtype
+  unsigned dtype_mask = 0;
+  size_t device_bytes = 0;
+  int device = 0;
+};
+
+// table.hip
+int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipStream_t st,
+                Model** out);
+void destroy_model(Model* m);
+
+// apply.hip
+const Layout& layout_for(const Model& m, bool adjoint, int dtype);
+size_t stage_bytes(const Model& m, bool adjoint, int dtype);
+// Apply A (adjoint = false) or A^T.  `in`/`out` are caller vectors of the dtype's element
+// type (double for FP64, float otherwise).  `stage` is a device buffer of at least
+// stage_bytes() bytes that the call may overwrite.
+int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* stage,
+          hipStream_t st);
+// Ragged batch: one launch per kernel class covering all requests.
+int apply_batch(int n, const Model* const* ms, bool adjoint, int dtype, const float* const* in,
+                float* const* out, hipStream_t st);
+
+// solvers.hip
+int solve_lsqr(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
+               aroam_solve_info* info, hipStream_t st);
+int solve_l1(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
+             aroam_solve_info* info, hipStream_t st);
+
+inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+inline long long round_up(long long a, long long b) { return ceil_div(a, b) * b; }
+
+}  // namespace aroam

@@ -1,0 +1,543 @@
+// Model construction: sensor sub-elements, footprint, FP64 table on the device, band tiles.
+//
+// The compressed model holds one scan position's columns (Methods, "Efficient
+// reconstruction based on scanning symmetries"): for every lateral offset o = (dx, dy) and
+// depth k inside the footprint, the time signal
+//     H[o][n, k] = sum_j dS_j / (2 pi r_j) e'((n - nt/2) - fs (r_j - R) / c)
+// of a point voxel (Eq. 1) seen by the sub-element sum of the spherical sensor (Eq. 3-4),
+// convolved with the electrical impulse response e (Results: IR = EIR * SIR).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace aroam {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMM = 1e3;
+constexpr double kCutoffSigmas = 5.0;
+
+// Sub-elements of the spherical cap (Eq. 3): equal-angle rings between the hole and the
+// rim; ring l is cut into a multiple of 8 equal patches (square-symmetric set) centred at
+// azimuth 2 pi (m + 1/2) / n_l; each patch has the exact zone area / n_l.  Positions are
+// relative to the focus in mm, with the sensor above the focal plane (negative z).
+void make_elements(const aroam_sensor& s, std::vector<double>& ex, std::vector<double>& ey,
+                   std::vector<double>& ez, std::vector<double>& area) {
+  const double R = s.radius_m * kMM;
+  const double th_m = std::asin(s.aperture_m / (2.0 * s.radius_m));
+  const double th_h = s.hole_m > 0 ? std::asin(s.hole_m / (2.0 * s.radius_m)) : 0.0;
+  const int nr = s.n_rings > 0 ? s.n_rings : 20;
+  const double dth = (th_m - th_h) / nr;
+  for (int l = 0; l < nr; ++l) {
+    const double t0 = th_h + (th_m - th_h) * l / nr;
+    const double t1 = th_h + (th_m - th_h) * (l + 1) / nr;
+    const double tb = 0.5 * (t0 + t1);
+    const int nl = 8 * std::max(1, (int)std::floor(2.0 * kPi * std::sin(tb) / (8.0 * dth) + 0.5));
+    const double a = R * R * (std::cos(t0) - std::cos(t1)) * 2.0 * kPi / nl;
+    for (int m = 0; m < nl; ++m) {
+      const double phi = 2.0 * kPi * (m + 0.5) / nl;
+      ex.push_back(R * std::sin(tb) * std::cos(phi));
+      ey.push_back(R * std::sin(tb) * std::sin(phi));
+      ez.push_back(-R * std::cos(tb));
+      area.push_back(a);
+    }
+  }
+}
+
+double depth_mm(const aroam_grid& g, int k) { return ((k - g.nz / 2) * g.dz_m) * kMM; }
+
+// Lateral footprint (Results, first paragraph; Methods, scanning symmetries): the model is
+// cut to |dx|, |dy| <= K, and in mode 1 to the cone (dx^2 + dy^2) step^2 <= rho(z)^2 with
+// rho(z) = 2 * 0.71 lambda / NA + |z| tan(theta_max).
+bool in_footprint(const aroam_sensor& s, const aroam_grid& g, int dx, int dy, int k) {
+  if (g.footprint_mode == 0) return true;
+  const double th_m = std::asin(s.aperture_m / (2.0 * s.radius_m));
+  const double na = std::sin(th_m);
+  const double rho0 = 2.0 * (0.71 * (g.c_mps / s.f0_hz) * kMM / na);
+  const double step = g.step_m * kMM;
+  const double rho = rho0 + std::fabs(depth_mm(g, k)) * std::tan(th_m);
+  return (double)(dx * dx + dy * dy) * step * step <= rho * rho;
+}
+
+struct Geo {
+  double step, R, cfs, sigma5, inv2s2, invs2, omega;
+  int nz, nt, M;
+  double dz_m;
+};
+
+// Distance-derived quantities of sub-element j for the voxel p (mm): the path difference
+// r - R is formed as (r^2 - R^2) / (r + R) with r^2 - R^2 = |p|^2 - 2 p.e + (|e|^2 - R^2), so
+// no digits cancel when r is close to R.
+__device__ inline void path(double px, double py, double pz, double p2, double ex, double ey,
+                            double ez, double eoff, double R, double& r, double& dr) {
+  const double q = p2 - 2.0 * (px * ex + py * ey + pz * ez) + eoff;
+  r = sqrt(R * R + q);
+  dr = q / (r + R);
+}
+
+__global__ void k_support(int n, const int* __restrict__ cdx, const int* __restrict__ cdy,
+                          const int* __restrict__ ck, const double* __restrict__ ex,
+                          const double* __restrict__ ey, const double* __restrict__ ez,
+                          const double* __restrict__ eoff, Geo geo, int* __restrict__ lo,
+                          int* __restrict__ hi) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double px = cdx[c] * geo.step, py = cdy[c] * geo.step;
+  const double pz = ((ck[c] - geo.nz / 2) * geo.dz_m) * 1e3;
+  const double p2 = px * px + py * py + pz * pz;
+  double dmin = 1e300, dmax = -1e300;
+  for (int j = 0; j < geo.M; ++j) {
+    double r, dr;
+    path(px, py, pz, p2, ex[j], ey[j], ez[j], eoff[j], geo.R, r, dr);
+    const double d = dr / geo.cfs;
+    dmin = fmin(dmin, d);
+    dmax = fmax(dmax, d);
+  }
+  const int h = geo.nt / 2;
+  int a = (int)ceil(h + dmin - geo.sigma5);
+  int b = (int)floor(h + dmax + geo.sigma5);
+  a = max(a, 0);
+  b = min(b, geo.nt - 1);
+  lo[c] = a <= b ? a : -1;
+  hi[c] = a <= b ? b : -1;
+}
+
+// One wave per active column: the wave first tabulates every sub-element's delay and
+// weight in LDS, then each lane sums the sub-elements for its time samples in FP64.
+__global__ __launch_bounds__(64) void k_table(const int* __restrict__ cdx,
+                                             const int* __restrict__ cdy,
+                                             const int* __restrict__ ck,
+                                             const int* __restrict__ lo,
+                                             const long long* __restrict__ off,
+                                             const double* __restrict__ ex,
+                                             const double* __restrict__ ey,
+                                             const double* __restrict__ ez,
+                                             const double* __restrict__ eoff,
+                                             const double* __restrict__ area, Geo geo,
+                                             double* __restrict__ band) {
+  extern __shared__ double sh[];  // [M] delay (samples), [M] weight dS / (2 pi r)
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double px = cdx[c] * geo.step, py = cdy[c] * geo.step;
+  const double pz = ((ck[c] - geo.nz / 2) * geo.dz_m) * 1e3;
+  const double p2 = px * px + py * py + pz * pz;
+  for (int j = lane; j < geo.M; j += 64) {
+    double r, dr;
+    path(px, py, pz, p2, ex[j], ey[j], ez[j], eoff[j], geo.R, r, dr);
+    sh[j] = dr / geo.cfs;
+    sh[geo.M + j] = area[j] / (2.0 * kPi * r);
+  }
+  __syncthreads();
+  const int l = lo[c];
+  const long long o = off[c];
+  const int len = (int)(off[c + 1] - o);
+  for (int i = lane; i < len; i += 64) {
+    const double nrel = (double)(l + i - geo.nt / 2);
+    double acc = 0.0;
+    for (int j = 0; j < geo.M; ++j) {
+      const double tau = nrel - sh[j];
+      if (fabs(tau) <= geo.sigma5) {
+        const double g = exp(-tau * tau * geo.inv2s2);
+        double sn, cs;
+        sincos(geo.omega * tau, &sn, &cs);
+        acc += sh[geo.M + j] * (-g * ((tau * geo.invs2) * cs + geo.omega * sn));
+      }
+    }
+    band[o + i] = acc;
+  }
+}
+
+// Fill band tiles: element (group, row m, entry j) of the pack is the table value at
+//   forward: time n = 16 tile + m, depth k = start + j
+//   adjoint: depth k = 16 tile + m, time n = start + j
+// of the group's offset, or 0 outside the footprint, the band or the grid.
+template <typename T>
+__device__ inline T cvt(double v);
+template <>
+__device__ inline double cvt<double>(double v) { return v; }
+template <>
+__device__ inline float cvt<float>(double v) { return (float)v; }
+template <>
+__device__ inline uint16_t cvt<uint16_t>(double v) {  // bf16, round to nearest even
+  float f = (float)v;
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ inline double table_value(int oi, int n, int k, int nz, int nt,
+                                     const int* __restrict__ colidx, const int* __restrict__ lo,
+                                     const long long* __restrict__ off,
+                                     const double* __restrict__ band) {
+  if (oi < 0 || n < 0 || n >= nt || k < 0 || k >= nz) return 0.0;
+  const int c = colidx[(long long)oi * nz + k];
+  if (c < 0) return 0.0;
+  const int l = lo[c];
+  const long long o = off[c];
+  const long long len = off[c + 1] - o;
+  if (n < l || n >= l + len) return 0.0;
+  return band[o + (n - l)];
+}
+
+template <typename T>
+__global__ void k_pack(long long total, int G, bool adjoint, const int4* __restrict__ groups,
+                       int nz, int nt, const int* __restrict__ colidx,
+                       const int* __restrict__ lo, const long long* __restrict__ off,
+                       const double* __restrict__ band, T* __restrict__ pack) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long grp = idx / (16 * G);
+    const int m = (int)((idx / G) % 16);
+    const int j = (int)(idx % G);
+    const int4 gd = groups[grp];  // (offset index, start, tile, active)
+    int n, k;
+    if (!adjoint) {
+      n = 16 * gd.z + m;
+      k = gd.y + j;
+    } else {
+      k = 16 * gd.z + m;
+      n = gd.y + j;
+    }
+    pack[idx] = cvt<T>(table_value(gd.x, n, k, nz, nt, colidx, lo, off, band));
+  }
+}
+
+template <typename T>
+int alloc_copy(T** dst, const std::vector<T>& src, size_t& bytes) {
+  const size_t b = std::max<size_t>(1, src.size()) * sizeof(T);
+  AROAM_HIP(hipMalloc((void**)dst, b));
+  bytes += b;
+  if (!src.empty()) AROAM_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return AROAM_OK;
+}
+
+PadGeom pad_geom(const aroam_grid& g, int L) {
+  PadGeom p;
+  p.K = g.k_half;
+  p.nx = g.nx;
+  p.ny = g.ny;
+  p.ntx = (int)ceil_div(g.nx, 16);
+  p.nxp = 16 * p.ntx + 2 * p.K;
+  p.nyp = g.ny + 2 * p.K;
+  p.L = L;
+  p.Lp = (int)round_up(L, 8) + 8;
+  return p;
+}
+
+// Build the K-group lists of one operator.  For output tile t (rows 16t .. 16t+15) and each
+// offset, the K-groups are the G-aligned runs of the inner axis that intersect some column's
+// band inside the tile; runs with no band entry are skipped; each tile's list is padded with
+// empty groups to a multiple of four (one bundle = four groups).
+int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes) {
+  const aroam_grid& g = m.grid;
+  const int K = m.K, W = 2 * K + 1, nz = g.nz, nt = g.nt;
+  lay.G = G;
+  lay.out_len = adjoint ? nz : nt;
+  lay.n_tiles = (int)ceil_div(lay.out_len, kTile);
+  lay.in = pad_geom(g, adjoint ? nt : nz);
+  const int inner = adjoint ? nt : nz;
+  std::vector<int4> groups;
+  std::vector<int> meta;
+  lay.h_tile_start.assign(lay.n_tiles + 1, 0);
+  std::vector<char> hit((size_t)ceil_div(inner, G) + 1);
+  for (int t = 0; t < lay.n_tiles; ++t) {
+    lay.h_tile_start[t] = (int)(groups.size() / kLaneGroups);
+    const int r0 = kTile * t, r1 = std::min(lay.out_len, r0 + kTile) - 1;
+    for (int oi = 0; oi < m.n_off; ++oi) {
+      const int dy = oi / W - K, dx = oi % W - K;
+      std::fill(hit.begin(), hit.end(), 0);
+      bool any = false;
+      if (!adjoint) {
+        for (int k = 0; k < nz; ++k) {
+          const int lo = m.h_lo[(size_t)oi * nz + k];
+          if (lo < 0) continue;
+          const int hi = m.h_hi[(size_t)oi * nz + k];
+          if (lo <= r1 && hi >= r0) {
+            hit[k / G] = 1;
+            any = true;
+          }
+        }
+      } else {
+        for (int k = r0; k <= r1; ++k) {
+          const int lo = m.h_lo[(size_t)oi * nz + k];
+          if (lo < 0) continue;
+          const int hi = m.h_hi[(size_t)oi * nz + k];
+          for (int q = lo / G; q <= hi / G; ++q) hit[q] = 1;
+          any = true;
+        }
+      }
+      if (!any) continue;
+      for (size_t q = 0; q < hit.size(); ++q) {
+        if (!hit[q]) continue;
+        const int start = (int)q * G;
+        groups.push_back(make_int4(oi, start, t, 1));
+        const long long delta =
+            adjoint ? ((long long)(-dy) * lay.in.nxp - dx) * lay.in.Lp + start
+                    : ((long long)dy * lay.in.nxp + dx) * lay.in.Lp + start;
+        meta.push_back((int)delta);
+      }
+    }
+    while (groups.size() % kLaneGroups) {
+      groups.push_back(make_int4(-1, 0, t, 0));
+      meta.push_back(0);
+    }
+  }
+  lay.h_tile_start[lay.n_tiles] = (int)(groups.size() / kLaneGroups);
+  lay.n_bundles = (long long)groups.size() / kLaneGroups;
+  lay.mac_exec = lay.n_bundles * kLaneGroups * kTile * G * (long long)g.ny * 16 * lay.in.ntx;
+  AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
+              "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
+  AROAM_TRY(alloc_copy(&lay.d_tile_start, lay.h_tile_start, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_meta, meta, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
+  return AROAM_OK;
+}
+
+template <typename T>
+int pack_dtype(const Model& m, const Layout& lay, bool adjoint, Pack& p, hipStream_t st,
+               size_t& bytes) {
+  const long long total = lay.n_bundles * kLaneGroups * kTile * lay.G;
+  p.bytes = std::max<long long>(1, total) * sizeof(T);
+  AROAM_HIP(hipMalloc(&p.d, p.bytes));
+  bytes += p.bytes;
+  if (total > 0) {
+    const int blocks = (int)std::min<long long>(ceil_div(total, 256), 1 << 16);
+    hipLaunchKernelGGL(k_pack<T>, dim3(blocks), dim3(256), 0, st, total, lay.G, adjoint,
+                       lay.d_groups, m.grid.nz, m.grid.nt, m.d_colidx, m.d_lo, m.d_off,
+                       m.d_band, (T*)p.d);
+    AROAM_HIP(hipGetLastError());
+  }
+  return AROAM_OK;
+}
+
+int build_impl(Model& m, hipStream_t st) {
+  const aroam_sensor& s = m.sensor;
+  const aroam_grid& g = m.grid;
+  const int K = m.K, W = 2 * K + 1, nz = g.nz;
+  size_t bytes = 0;
+
+  std::vector<double> ex, ey, ez, area;
+  make_elements(s, ex, ey, ez, area);
+  m.M = (int)area.size();
+  AROAM_CHECK(m.M <= kMaxElements, AROAM_EINVAL, "%d sub-elements exceed the limit of %d", m.M,
+              kMaxElements);
+  m.R_mm = s.radius_m * kMM;
+  std::vector<double> eoff(m.M);
+  for (int j = 0; j < m.M; ++j)
+    eoff[j] = ex[j] * ex[j] + ey[j] * ey[j] + ez[j] * ez[j] - m.R_mm * m.R_mm;
+  const double sigma_f = s.f0_hz * s.frac_bw / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+  m.sigma = g.fs_hz / (2.0 * kPi * sigma_f);
+  m.omega = 2.0 * kPi * s.f0_hz / g.fs_hz;
+  m.cfs = g.c_mps * kMM / g.fs_hz;
+  m.step_mm = g.step_m * kMM;
+  m.dz_mm = g.dz_m * kMM;
+
+  // footprint columns, in (dy, dx, k) order
+  std::vector<int> fdx, fdy, fk, foi;
+  for (int a = 0; a < W; ++a)
+    for (int b = 0; b < W; ++b)
+      for (int k = 0; k < nz; ++k)
+        if (in_footprint(s, g, b - K, a - K, k)) {
+          fdx.push_back(b - K);
+          fdy.push_back(a - K);
+          fk.push_back(k);
+          foi.push_back(a * W + b);
+        }
+  const int nf = (int)fk.size();
+
+  Geo geo;
+  geo.step = m.step_mm;
+  geo.R = m.R_mm;
+  geo.cfs = m.cfs;
+  geo.sigma5 = kCutoffSigmas * m.sigma;
+  geo.inv2s2 = 1.0 / (2.0 * m.sigma * m.sigma);
+  geo.invs2 = 1.0 / (m.sigma * m.sigma);
+  geo.omega = m.omega;
+  geo.nz = nz;
+  geo.nt = g.nt;
+  geo.M = m.M;
+  geo.dz_m = g.dz_m;
+
+  double *d_ex = nullptr, *d_ey = nullptr, *d_ez = nullptr, *d_eoff = nullptr, *d_area = nullptr;
+  int *d_fdx = nullptr, *d_fdy = nullptr, *d_fk = nullptr, *d_flo = nullptr, *d_fhi = nullptr;
+  size_t tmp = 0;
+  int rc = AROAM_OK;
+  auto cleanup = [&]() {
+    (void)hipFree(d_ex); (void)hipFree(d_ey); (void)hipFree(d_ez); (void)hipFree(d_eoff); (void)hipFree(d_area);
+    (void)hipFree(d_fdx); (void)hipFree(d_fdy); (void)hipFree(d_fk); (void)hipFree(d_flo); (void)hipFree(d_fhi);
+  };
+  do {
+    if ((rc = alloc_copy(&d_ex, ex, tmp))) break;
+    if ((rc = alloc_copy(&d_ey, ey, tmp))) break;
+    if ((rc = alloc_copy(&d_ez, ez, tmp))) break;
+    if ((rc = alloc_copy(&d_eoff, eoff, tmp))) break;
+    if ((rc = alloc_copy(&d_area, area, tmp))) break;
+    if ((rc = alloc_copy(&d_fdx, fdx, tmp))) break;
+    if ((rc = alloc_copy(&d_fdy, fdy, tmp))) break;
+    if ((rc = alloc_copy(&d_fk, fk, tmp))) break;
+    std::vector<int> zeros(nf, 0);
+    if ((rc = alloc_copy(&d_flo, zeros, tmp))) break;
+    if ((rc = alloc_copy(&d_fhi, zeros, tmp))) break;
+    if (nf > 0) {
+      hipLaunchKernelGGL(k_support, dim3((unsigned)ceil_div(nf, 128)), dim3(128), 0, st, nf,
+                         d_fdx, d_fdy, d_fk, d_ex, d_ey, d_ez, d_eoff, geo, d_flo, d_fhi);
+      if (hipGetLastError() != hipSuccess) { set_error("support kernel launch failed"); rc = AROAM_EDEVICE; break; }
+    }
+    std::vector<int> flo(nf), fhi(nf);
+    if (nf > 0) {
+      if (hipMemcpyAsync(flo.data(), d_flo, nf * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(fhi.data(), d_fhi, nf * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        set_error("support download failed");
+        rc = AROAM_EDEVICE;
+        break;
+      }
+    }
+    // active columns: footprint columns with a non-empty window
+    m.h_lo.assign((size_t)m.n_off * nz, -1);
+    m.h_hi.assign((size_t)m.n_off * nz, -1);
+    m.h_colidx.assign((size_t)m.n_off * nz, -1);
+    std::vector<int> adx, ady, ak, alo;
+    m.h_off.clear();
+    m.h_off.push_back(0);
+    m.mac_alg = 0;
+    for (int c = 0; c < nf; ++c) {
+      if (flo[c] < 0) continue;
+      const size_t key = (size_t)foi[c] * nz + fk[c];
+      m.h_lo[key] = flo[c];
+      m.h_hi[key] = fhi[c];
+      m.h_colidx[key] = (int)alo.size();
+      adx.push_back(fdx[c]);
+      ady.push_back(fdy[c]);
+      ak.push_back(fk[c]);
+      alo.push_back(flo[c]);
+      const long long len = fhi[c] - flo[c] + 1;
+      m.h_off.push_back(m.h_off.back() + len);
+      const long long pairs = (long long)std::max(0, g.ny - std::abs(fdy[c])) *
+                              std::max(0, g.nx - std::abs(fdx[c]));
+      m.mac_alg += pairs * len;
+    }
+    m.n_columns = (long long)alo.size();
+    m.nnz = m.h_off.back();
+    if ((rc = alloc_copy(&m.d_colidx, m.h_colidx, bytes))) break;
+    if ((rc = alloc_copy(&m.d_lo, alo, bytes))) break;
+    if ((rc = alloc_copy(&m.d_off, m.h_off, bytes))) break;
+    const size_t band_bytes = std::max<long long>(1, m.nnz) * sizeof(double);
+    if (hipMalloc((void**)&m.d_band, band_bytes) != hipSuccess) { set_error("out of device memory for the table"); rc = AROAM_ENOMEM; break; }
+    bytes += band_bytes;
+    int *d_adx = nullptr, *d_ady = nullptr, *d_ak = nullptr;
+    if ((rc = alloc_copy(&d_adx, adx, tmp)) || (rc = alloc_copy(&d_ady, ady, tmp)) ||
+        (rc = alloc_copy(&d_ak, ak, tmp))) {
+      (void)hipFree(d_adx); (void)hipFree(d_ady); (void)hipFree(d_ak);
+      break;
+    }
+    if (m.n_columns > 0) {
+      hipLaunchKernelGGL(k_table, dim3((unsigned)m.n_columns), dim3(64), 2 * m.M * sizeof(double),
+                         st, d_adx, d_ady, d_ak, m.d_lo, m.d_off, d_ex, d_ey, d_ez, d_eoff,
+                         d_area, geo, m.d_band);
+      if (hipGetLastError() != hipSuccess) { set_error("table kernel launch failed"); rc = AROAM_EDEVICE; }
+    }
+    if (rc == AROAM_OK && hipStreamSynchronize(st) != hipSuccess) { set_error("table build failed"); rc = AROAM_EDEVICE; }
+    (void)hipFree(d_adx); (void)hipFree(d_ady); (void)hipFree(d_ak);
+  } while (false);
+  cleanup();
+  if (rc) return rc;
+
+  // band tiles
+  AROAM_TRY(build_layout(m, false, 4, m.fwd4, bytes));
+  AROAM_TRY(build_layout(m, true, 4, m.adj4, bytes));
+  AROAM_TRY(pack_dtype<double>(m, m.fwd4, false, m.fwd_pack[AROAM_FP64], st, bytes));
+  AROAM_TRY(pack_dtype<double>(m, m.adj4, true, m.adj_pack[AROAM_FP64], st, bytes));
+  AROAM_TRY(pack_dtype<float>(m, m.fwd4, false, m.fwd_pack[AROAM_FP32], st, bytes));
+  AROAM_TRY(pack_dtype<float>(m, m.adj4, true, m.adj_pack[AROAM_FP32], st, bytes));
+  m.dtype_mask = (1u << AROAM_FP64) | (1u << AROAM_FP32);
+  return AROAM_OK;
+}
+
+}  // namespace
+
+int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipStream_t st,
+                Model** out) {
+  AROAM_CHECK(s && g && out, AROAM_EINVAL, "NULL argument to aroam_build_model");
+  *out = nullptr;
+  AROAM_CHECK(s->radius_m > 0 && s->aperture_m > 0 && s->aperture_m <= 2 * s->radius_m &&
+                  s->hole_m >= 0 && s->hole_m < s->aperture_m && s->f0_hz > 0 &&
+                  s->frac_bw > 0 && s->n_rings >= 0 && s->n_rings <= 1000,
+              AROAM_EINVAL, "invalid sensor geometry");
+  AROAM_CHECK(g->c_mps > 0 && g->fs_hz > 0 && g->step_m > 0 && g->dz_m > 0, AROAM_EINVAL,
+              "invalid grid spacing");
+  AROAM_CHECK(g->nx >= 1 && g->ny >= 1 && g->nz >= 1 && g->nt >= 1 && g->nx <= 65536 &&
+                  g->ny <= 65536 && g->nz <= 65536 && g->nt <= 65536,
+              AROAM_EINVAL, "grid sizes out of range");
+  AROAM_CHECK(g->k_half >= 0 && g->k_half <= 256, AROAM_EINVAL, "k_half out of range");
+  AROAM_CHECK(g->footprint_mode == 0 || g->footprint_mode == 1, AROAM_EINVAL,
+              "footprint_mode must be 0 or 1");
+  Model* m = new (std::nothrow) Model();
+  AROAM_CHECK(m, AROAM_ENOMEM, "host allocation failed");
+  m->sensor = *s;
+  m->grid = *g;
+  m->K = g->k_half;
+  m->n_off = (2 * g->k_half + 1) * (2 * g->k_half + 1);
+  (void)hipGetDevice(&m->device);
+  int rc = build_impl(*m, st);
+  if (rc == AROAM_OK) {
+    const bool want8 = (mask & ((1u << AROAM_BF16) | (1u << AROAM_FP8E4M3))) != 0;
+    size_t bytes = 0;
+    if (want8) {
+      rc = build_layout(*m, false, 8, m->fwd8, bytes);
+      if (!rc) rc = build_layout(*m, true, 8, m->adj8, bytes);
+    }
+    if (!rc && (mask & (1u << AROAM_BF16))) {
+      rc = pack_dtype<uint16_t>(*m, m->fwd8, false, m->fwd_pack[AROAM_BF16], st, bytes);
+      if (!rc) rc = pack_dtype<uint16_t>(*m, m->adj8, true, m->adj_pack[AROAM_BF16], st, bytes);
+      if (!rc) m->dtype_mask |= 1u << AROAM_BF16;
+    }
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) {
+      set_error("model packing failed");
+      rc = AROAM_EDEVICE;
+    }
+  }
+  if (rc != AROAM_OK) {
+    destroy_model(m);
+    return rc;
+  }
+  // account device memory
+  size_t b = (size_t)std::max<long long>(1, m->nnz) * sizeof(double);
+  b += m->h_colidx.size() * sizeof(int) + m->n_columns * sizeof(int) + m->h_off.size() * 8;
+  for (const Layout* l : {&m->fwd4, &m->adj4, &m->fwd8, &m->adj8})
+    b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) + l->h_tile_start.size() * 4;
+  for (int d = 0; d < 4; ++d) b += m->fwd_pack[d].bytes + m->adj_pack[d].bytes;
+  m->device_bytes = b;
+  *out = m;
+  return AROAM_OK;
+}
+
+void destroy_model(Model* m) {
+  if (!m) return;
+  (void)hipFree(m->d_band);
+  (void)hipFree(m->d_colidx);
+  (void)hipFree(m->d_lo);
+  (void)hipFree(m->d_off);
+  for (Layout* l : {&m->fwd4, &m->adj4, &m->fwd8, &m->adj8}) {
+    (void)hipFree(l->d_tile_start);
+    (void)hipFree(l->d_meta);
+    (void)hipFree(l->d_groups);
+  }
+  for (int d = 0; d < 4; ++d) {
+    (void)hipFree(m->fwd_pack[d].d);
+    (void)hipFree(m->fwd_pack[d].d_scale);
+    (void)hipFree(m->adj_pack[d].d);
+    (void)hipFree(m->adj_pack[d].d_scale);
+  }
+  delete m;
+}
+
+}  // namespace aroam

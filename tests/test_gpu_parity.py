@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on the same
+seeded inputs.  Tolerances: FP64 <= 1e-12 (relative to the largest entry / L2 norm), FP32
+apply <= 1e-5 relative L2, FP32 reconstruction <= 1e-4 relative L2."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import model as omodel
+from oracle import operators as oops
+from oracle import solvers as osol
+from tests.helpers import (oracle_ops, oracle_signals, oracle_supports, oracle_table, rel_l2,
+                           rel_max)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2009_10173_amd as P  # noqa: E402
+
+SMALL = ["tiny", "mid", "mid7"]
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+_MODELS = {}
+
+
+def gpu_model(name, dtypes=("fp64", "fp32", "bf16")):
+    key = (name, tuple(dtypes))
+    if key not in _MODELS:
+        cfg = W.config(name)
+        print(f"[build model {name} {dtypes}]", flush=True)
+        _MODELS[key] = P.Model(cfg["sensor"], cfg["grid"], dtypes=dtypes)
+    return _MODELS[key]
+
+
+def t64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(_dev())
+
+
+def t32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(_dev())
+
+
+# --- table --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", SMALL)
+def test_table_matches_oracle(name):
+    m = gpu_model(name)
+    H, lo, hi = m.export_table()
+    olo, ohi = oracle_supports(name)
+    assert np.array_equal(lo, olo) and np.array_equal(hi, ohi)
+    ref = oracle_table(name)
+    assert rel_max(H, ref) <= 1e-12
+    info = m.info()
+    cfg = W.config(name)
+    assert info["mac_alg"] == oops.mac_alg(cfg["grid"], olo, ohi)
+    assert info["nnz"] == int(np.sum(np.where(olo >= 0, ohi - olo + 1, 0)))
+    assert info["n_elements"] == len(omodel.sensor_elements(cfg["sensor"])[1])
+
+
+# --- applies ------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", SMALL)
+def test_forward_adjoint_fp64(name):
+    cfg = W.config(name)
+    m = gpu_model(name)
+    H = oracle_table(name)
+    x = W.random_image(cfg, 11)
+    y = W.random_signal(cfg, 11)
+    s_ref = oops.forward(H, x)
+    x_ref = oops.adjoint(H, y)
+    s = m.forward(t64(x), "fp64").cpu().numpy()
+    xa = m.adjoint(t64(y), "fp64").cpu().numpy()
+    assert rel_max(s, s_ref) <= 1e-12
+    assert rel_max(xa, x_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_forward_adjoint_fp32(name):
+    cfg = W.config(name)
+    m = gpu_model(name)
+    H = oracle_table(name)
+    x = W.random_image(cfg, 12)
+    y = W.random_signal(cfg, 12)
+    s = m.forward(t32(x), "fp32").cpu().numpy()
+    xa = m.adjoint(t32(y), "fp32").cpu().numpy()
+    assert rel_l2(s, oops.forward(H, x.astype(np.float32))) <= 1e-5
+    assert rel_l2(xa, oops.adjoint(H, y.astype(np.float32))) <= 1e-5
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_forward_adjoint_bf16_reported(name):
+    """BF16 operands with FP32 accumulation: error vs the FP64 oracle is reported; the
+    bound 1e-2 is the size of two BF16 roundings (2^-8 each) with random-sign errors."""
+    cfg = W.config(name)
+    m = gpu_model(name)
+    H = oracle_table(name)
+    x0, _ = oracle_signals(name)
+    y = W.random_signal(cfg, 13)
+    e_f = rel_l2(m.forward(t32(x0), "bf16").cpu().numpy(), oops.forward(H, x0))
+    e_a = rel_l2(m.adjoint(t32(y), "bf16").cpu().numpy(), oops.adjoint(H, y))
+    print(f"[bf16 {name}] forward rel L2 {e_f:.2e} adjoint rel L2 {e_a:.2e}")
+    assert e_f <= 1e-2 and e_a <= 1e-2
+
+
+@pytest.mark.parametrize("name,dtype", [("mid", "fp64"), ("mid", "fp32"), ("mid7", "fp32")])
+def test_adjoint_identity_on_gpu(name, dtype):
+    cfg = W.config(name)
+    m = gpu_model(name)
+    conv = t64 if dtype == "fp64" else t32
+    x = conv(W.random_image(cfg, 14))
+    y = conv(W.random_signal(cfg, 14))
+    Ax = m.forward(x, dtype).double()
+    ATy = m.adjoint(y, dtype).double()
+    lhs = torch.dot(Ax.ravel(), y.double().ravel()).item()
+    rhs = torch.dot(x.double().ravel(), ATy.ravel()).item()
+    tol = 1e-13 if dtype == "fp64" else 1e-6
+    assert abs(lhs - rhs) <= tol * Ax.norm().item() * y.double().norm().item()
+
+
+def test_applies_are_deterministic():
+    cfg = W.config("mid")
+    m = gpu_model("mid")
+    x = t32(W.random_image(cfg, 15))
+    y = t32(W.random_signal(cfg, 15))
+    for dt in ("fp32", "bf16"):
+        a1, a2 = m.forward(x, dt), m.forward(x, dt)
+        b1, b2 = m.adjoint(y, dt), m.adjoint(y, dt)
+        assert torch.equal(a1, a2) and torch.equal(b1, b2)
+
+
+def test_full_size_depth_slabs_fp32():
+    """Full-size 200x200 scan, 128 depths, Nt 512, cone up to 41x41, in the launch
+    configuration the bench times.  The oracle evaluates two depth slabs: a forward of an
+    image that is nonzero only at those depths, and the adjoint's output at those depths."""
+    name = "vessels200"
+    cfg = W.config(name)
+    g = cfg["grid"]
+    m = gpu_model(name, ("fp32",))
+    ks = [23, 90]
+    Hs = omodel.build_table(cfg["sensor"], g, depths=ks)[:, :, ks, :]
+    rng = W.rng(77)
+    x = np.zeros((g["ny"], g["nx"], g["nz"]), dtype=np.float32)
+    x[:, :, ks] = rng.standard_normal((g["ny"], g["nx"], len(ks)))
+    s = m.forward(t32(x), "fp32").cpu().numpy()
+    s_ref = oops.forward(Hs, x[:, :, ks].astype(np.float64))
+    assert rel_l2(s, s_ref) <= 1e-5
+    y = rng.standard_normal((g["ny"], g["nx"], g["nt"])).astype(np.float32)
+    xa = m.adjoint(t32(y), "fp32").cpu().numpy()[:, :, ks]
+    xa_ref = oops.adjoint(Hs, y.astype(np.float64))
+    assert rel_l2(xa, xa_ref) <= 1e-5
+
+
+# --- solvers ------------------------------------------------------------------------------
+
+def test_lsqr_fp64_tiny_matches_oracle():
+    name = "tiny"
+    cfg = W.config(name)
+    m = gpu_model(name)
+    _, s = oracle_signals(name)
+    A, AT = oracle_ops(name)
+    iters = cfg["solver"]["iters"]
+    x_ref, hist = osol.lsqr(A, AT, s.ravel(), damp=0.0, iters=iters)
+    x, info = m.solve_lsqr(t64(s), lam=0.0, iters=iters, inner="fp64")
+    assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-10
+    assert info["iters_done"] == iters
+    assert abs(info["alpha"] - hist[-1]["alpha"]) <= 1e-10 * hist[-1]["alpha"]
+
+
+@pytest.mark.parametrize("name", ["mid", "mid7"])
+def test_lsqr_tikhonov_fp32_matches_oracle(name):
+    cfg = W.config(name)
+    m = gpu_model(name)
+    _, s = oracle_signals(name)
+    A, AT = oracle_ops(name)
+    iters = 30
+    lam = osol.lam_l2(AT(s.ravel()))
+    x_ref, _ = osol.lsqr(A, AT, s.ravel(), damp=math.sqrt(lam), iters=iters)
+    x, info = m.solve_lsqr(t32(s), lam=-1.0, iters=iters, inner="fp32")
+    assert abs(info["lam"] - lam) <= 1e-5 * lam
+    assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-4
+    x64, info64 = m.solve_lsqr(t64(s), lam=lam, iters=iters, inner="fp64")
+    assert rel_l2(x64.cpu().numpy(), x_ref) <= 1e-10
+
+
+def _fista_ref(name, iters):
+    cfg = W.config(name)
+    _, s = oracle_signals(name)
+    A, AT = oracle_ops(name)
+    sig2 = osol.power_iteration(A, AT, W.start_vector(cfg, 0), iters=50)
+    L = osol.lipschitz(sig2)
+    lam = osol.lam_l1(AT(s.ravel()))
+    x_ref, _ = osol.fista(A, AT, s.ravel(), lam, L, iters)
+    return s, L, lam, x_ref
+
+
+def test_fista_fp64_matches_oracle():
+    name = "pairs16"
+    cfg = W.config(name)
+    m = gpu_model(name)
+    s, L, lam, x_ref = _fista_ref(name, 200)
+    x, info = m.solve_l1(t64(s), lam=-1.0, iters=200, inner="fp64",
+                         power_start=t64(W.start_vector(cfg, 0)))
+    assert abs(info["lipschitz"] - L) <= 1e-10 * L
+    assert abs(info["lam"] - lam) <= 1e-12 * lam
+    assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["pairs16", "mid7"])
+def test_fista_fp32_matches_oracle(name):
+    cfg = W.config(name)
+    m = gpu_model(name)
+    iters = 200 if name == "pairs16" else 60
+    s, L, lam, x_ref = _fista_ref(name, iters)
+    x, info = m.solve_l1(t32(s), lam=lam, iters=iters, inner="fp32", lipschitz=L)
+    assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-4
+    xp, infop = m.solve_l1(t32(s), lam=-1.0, iters=iters, inner="fp32",
+                           power_start=t32(W.start_vector(cfg, 0)))
+    assert abs(infop["lipschitz"] - L) <= 1e-5 * L
+
+
+# --- failure handling -------------------------------------------------------------------
+
+def test_nonfinite_signal_is_reported():
+    cfg = W.config("tiny")
+    m = gpu_model("tiny")
+    s = W.random_signal(cfg, 3)
+    s[3, 4, 10] = np.nan
+    with pytest.raises(P.AroamError) as e:
+        m.solve_lsqr(t32(s), lam=0.0, iters=5, inner="fp32")
+    assert e.value.status == -4
+
+
+def test_unpacked_dtype_is_rejected():
+    cfg = W.config("tiny")
+    m = gpu_model("tiny", ("fp32",))
+    x = t32(W.random_image(cfg, 1))
+    with pytest.raises(P.AroamError) as e:
+        m.forward(x, "bf16")
+    assert e.value.status == -5
+
+
+def test_bad_grid_is_rejected():
+    cfg = W.config("tiny")
+    g = dict(cfg["grid"], nx=0)
+    with pytest.raises(P.AroamError) as e:
+        P.Model(cfg["sensor"], g)
+    assert e.value.status == -1
