@@ -26,7 +26,6 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kWaves = 4;  // waves per workgroup in the MFMA kernels
 
 template <typename Tin, typename Tout>
 __device__ inline Tout conv(Tin v);
@@ -90,30 +89,91 @@ __global__ __launch_bounds__(256) void k_apply_fma(const T* __restrict__ pack, c
   if (row < a.out_len && px < a.nx) out[((long long)py * a.nx + px) * a.out_len + row] = acc;
 }
 
-// Operand bases of the NT 16-position tiles handled by one wave.  Tiles past the end of
-// the grid point at tile 0 (a valid address) and are not stored.
-template <int NT>
-__device__ inline void tile_bases(const ApplyArgs& a, int t0, int n, long long* base, int* py,
-                                  int* px) {
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    int idx = t0 + t;
-    const bool ok = idx < a.n_ntiles;
-    if (!ok) idx = 0;
-    const int y = idx / a.ntx, tx = idx % a.ntx;
-    base[t] = ((long long)(y + a.K) * a.nxp + 16 * tx + n + a.K) * a.Lp;
-    py[t] = ok ? y : -1;
-    px[t] = 16 * tx + n;
-  }
-}
+struct StagedArgs {
+  const int* tile_units;
+  const int4* units;
+  const int2* ucols;
+  const int* meta;
+  int out_len, nx, ny, K, nxp, Lp;
+  int ncc;         // patch column chunks
+  int NCOL, CS, CH;
+};
 
-template <int NT>
-__device__ inline void store_tile(const ApplyArgs& a, float* __restrict__ out, int tile, int g,
-                                  const floatx4* acc, const int* py, const int* px) {
+// LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 rows) and one patch
+// of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT 16-position
+// tiles.  Per stage unit (dy, chunk) the patch's input rows shifted by dy, the unit's column
+// window and the chunk's CH inner entries are copied to LDS; then every bundle of the unit
+// multiplies the 16 x (4 G) table block (from global memory, shared by the 4 waves through
+// L1) with the NT position tiles read from LDS.  Lane (n = lane % 16, g = lane / 16) holds
+// row n of K-group g of the table and the entries of K-group g for position n.
+template <typename T, int BR, int BC>
+__global__ __launch_bounds__(256) void k_apply_staged(const T* __restrict__ pack,
+                                                      const T* __restrict__ in,
+                                                      float* __restrict__ out, StagedArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  constexpr int VEC = 16 / sizeof(T);  // entries per 16-byte vector == K-group width G
+  constexpr int TPR = BC / 16;
+  constexpr int RW = BR / 4;
+  constexpr int NT = RW * TPR;
+  const int tile = blockIdx.y;
+  const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int n = lane % 16, g = lane / 16;
+  int lbase[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    if (py[t] < 0 || px[t] >= a.nx) continue;
-    float* o = out + ((long long)py[t] * a.nx + px[t]) * a.out_len;
+    const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
+    lbase[t] = (r * a.NCOL + c) * a.CS;
+  }
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int u0 = a.tile_units[tile], u1 = a.tile_units[tile + 1];
+  const int nvec = a.CH / VEC;
+  for (int u = u0; u < u1; ++u) {
+    const int4 U = a.units[u];   // (row offset, chunk start, bundle begin, bundle end)
+    const int2 C = a.ucols[u];   // staged columns [C.x, C.y)
+    const int ncols = C.y - C.x;
+    const int total = BR * ncols * nvec;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < total; idx += 256) {
+      const int v = idx % nvec;
+      const int rc = idx / nvec;
+      const int c = C.x + rc % ncols, r = rc / ncols;
+      const long long src =
+          ((long long)(py0 + r + U.x + a.K) * a.nxp + (px0 + c)) * a.Lp + U.y + v * VEC;
+      *reinterpret_cast<uint4*>(lds + (r * a.NCOL + c) * a.CS + v * VEC) =
+          *reinterpret_cast<const uint4*>(in + src);
+    }
+    __syncthreads();
+    for (int b = U.z; b < U.w; ++b) {
+      const int q = b * kLaneGroups + g;
+      const uint4 araw = *reinterpret_cast<const uint4*>(pack + ((long long)q * 16 + n) * VEC);
+      const int mo = a.meta[q];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const uint4 xraw = *reinterpret_cast<const uint4*>(lds + lbase[t] + mo);
+        if constexpr (sizeof(T) == 4) {
+          const float4 av = *reinterpret_cast<const float4*>(&araw);
+          const float4 xv = *reinterpret_cast<const float4*>(&xraw);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[t], 0, 0, 0);
+        } else {
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&araw);
+          const bf16x8 xv = *reinterpret_cast<const bf16x8*>(&xraw);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int py = py0 + wave * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
+    if (py >= a.ny || px >= a.nx) continue;
+    float* o = out + ((long long)py * a.nx + px) * a.out_len;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = kTile * tile + 4 * g + i;
@@ -121,72 +181,6 @@ __device__ inline void store_tile(const ApplyArgs& a, float* __restrict__ out, i
     }
   }
 }
-
-// FP32 MFMA kernel.  Lane (n = lane % 16, g = lane / 16) holds, per bundle, row n of
-// K-group g of the table (4 entries = one float4) and entries of K-group g for position n of
-// each of the wave's NT position tiles; four 16x16x4 MFMAs consume one bundle per tile.
-template <int NT>
-__global__ __launch_bounds__(256) void k_apply_f32(const float* __restrict__ pack,
-                                                   const float* __restrict__ in,
-                                                   float* __restrict__ out, ApplyArgs a) {
-  const int tile = blockIdx.y;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int n = lane % 16, g = lane / 16;
-  const int t0 = (blockIdx.x * kWaves + wave) * NT;
-  long long base[NT];
-  int py[NT], px[NT];
-  tile_bases<NT>(a, t0, n, base, py, px);
-  floatx4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int b0 = a.tile_start[tile], b1 = a.tile_start[tile + 1];
-  for (int b = b0; b < b1; ++b) {
-    const int q = b * kLaneGroups + g;
-    const float4 av = *reinterpret_cast<const float4*>(pack + ((long long)q * 16 + n) * 4);
-    const int d = a.meta[q];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const float4 xv = *reinterpret_cast<const float4*>(in + base[t] + d);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[t], 0, 0, 0);
-    }
-  }
-  store_tile<NT>(a, out, tile, g, acc, py, px);
-}
-
-// BF16 MFMA kernel: lane (n, g) holds the 8 entries of K-group g (one 16-byte load per
-// operand); one 16x16x32 MFMA consumes one bundle per position tile.
-template <int NT>
-__global__ __launch_bounds__(256) void k_apply_bf16(const uint16_t* __restrict__ pack,
-                                                    const uint16_t* __restrict__ in,
-                                                    float* __restrict__ out, ApplyArgs a) {
-  const int tile = blockIdx.y;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int n = lane % 16, g = lane / 16;
-  const int t0 = (blockIdx.x * kWaves + wave) * NT;
-  long long base[NT];
-  int py[NT], px[NT];
-  tile_bases<NT>(a, t0, n, base, py, px);
-  floatx4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int b0 = a.tile_start[tile], b1 = a.tile_start[tile + 1];
-  for (int b = b0; b < b1; ++b) {
-    const int q = b * kLaneGroups + g;
-    const bf16x8 av = *reinterpret_cast<const bf16x8*>(pack + ((long long)q * 16 + n) * 8);
-    const int d = a.meta[q];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const bf16x8 xv = *reinterpret_cast<const bf16x8*>(in + base[t] + d);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[t], 0, 0, 0);
-    }
-  }
-  store_tile<NT>(a, out, tile, g, acc, py, px);
-}
-
-constexpr int kNT = 4;  // position tiles per wave
 
 ApplyArgs make_args(const Layout& lay) {
   ApplyArgs a;
@@ -214,15 +208,52 @@ size_t elem_bytes(int dtype) {
 }  // namespace
 
 const Layout& layout_for(const Model& m, bool adjoint, int dtype) {
-  const bool wide = dtype == AROAM_FP64 || dtype == AROAM_FP32;
-  if (adjoint) return wide ? m.adj4 : m.adj8;
-  return wide ? m.fwd4 : m.fwd8;
+  if (dtype == AROAM_FP64) return adjoint ? m.g4a : m.g4f;
+  if (dtype == AROAM_FP32) return adjoint ? m.s4a : m.s4f;
+  return adjoint ? m.s8a : m.s8f;
 }
 
 size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
   const Layout& lay = layout_for(m, adjoint, dtype);
   return (size_t)round_up(lay.in.elems() * elem_bytes(dtype), 256);
 }
+
+namespace {
+
+template <typename T>
+int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out, hipStream_t st) {
+  static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
+  auto kern = k_apply_staged<T, kPatchRows, kPatchCols>;
+  static bool attr_set = false;  // allow the full LDS of a CU for wide footprints
+  if (!attr_set) {
+    AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024));
+    attr_set = true;
+  }
+  AROAM_CHECK(lay.lds_bytes <= 160 * 1024, AROAM_EINVAL,
+              "lateral footprint too wide for the LDS stage (%zu bytes)", lay.lds_bytes);
+  StagedArgs a;
+  a.tile_units = lay.d_tile_units;
+  a.units = lay.d_units;
+  a.ucols = lay.d_ucols;
+  a.meta = lay.d_meta;
+  a.out_len = lay.out_len;
+  a.nx = lay.in.nx;
+  a.ny = lay.in.ny;
+  a.K = lay.in.K;
+  a.nxp = lay.in.nxp;
+  a.Lp = lay.in.Lp;
+  a.ncc = (int)ceil_div(lay.in.nx, kPatchCols);
+  a.NCOL = lay.NCOL;
+  a.CS = lay.CS;
+  a.CH = lay.CH;
+  const dim3 grid((unsigned)(ceil_div(lay.in.ny, kPatchRows) * a.ncc), (unsigned)lay.n_tiles);
+  hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const T*)pk.d, (const T*)buf,
+                     (float*)out, a);
+  return AROAM_OK;
+}
+
+}  // namespace
 
 int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* stage,
           hipStream_t st) {
@@ -246,19 +277,15 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
   else
     hipLaunchKernelGGL((k_stage<float, uint16_t>), sgrid, dim3(256), 0, st, (const float*)in,
                        (uint16_t*)buf, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp);
-  const ApplyArgs a = make_args(lay);
   if (dtype == AROAM_FP64) {
+    const ApplyArgs a = make_args(lay);
     const dim3 grid((unsigned)a.n_ntiles, (unsigned)lay.n_tiles);
     hipLaunchKernelGGL(k_apply_fma<double>, grid, dim3(256), 0, st, (const double*)pk.d,
                        (const double*)buf, (double*)out, a, lay.G);
+  } else if (dtype == AROAM_FP32) {
+    AROAM_TRY(launch_staged<float>(lay, pk, buf, out, st));
   } else {
-    const dim3 grid((unsigned)ceil_div(a.n_ntiles, kWaves * kNT), (unsigned)lay.n_tiles);
-    if (dtype == AROAM_FP32)
-      hipLaunchKernelGGL(k_apply_f32<kNT>, grid, dim3(64 * kWaves), 0, st, (const float*)pk.d,
-                         (const float*)buf, (float*)out, a);
-    else
-      hipLaunchKernelGGL(k_apply_bf16<kNT>, grid, dim3(64 * kWaves), 0, st,
-                         (const uint16_t*)pk.d, (const uint16_t*)buf, (float*)out, a);
+    AROAM_TRY(launch_staged<uint16_t>(lay, pk, buf, out, st));
   }
   AROAM_HIP(hipGetLastError());
   if (!stage) AROAM_HIP(hipFreeAsync(buf, st));

@@ -42,6 +42,8 @@ void clear_error();
 
 constexpr int kTile = 16;     // output rows per tile (time samples or depths) = MFMA M
 constexpr int kLaneGroups = 4; // K-groups per bundle = 64-lane wave / 16
+constexpr int kPatchRows = 8;   // scan rows per workgroup patch of the staged kernels
+constexpr int kPatchCols = 32;  // scan columns per workgroup patch (two 16-position tiles)
 constexpr int kMaxElements = 4096;  // two FP64 values per sub-element fit in 64 KiB of LDS
 
 // ------------------------------------------------------------------------------------------
@@ -59,17 +61,35 @@ struct PadGeom {
 // Band tiles of one operator (forward: rows = time, K = (offset, depth); adjoint: rows =
 // depth, K = (offset, time)) at one K-group width G.  A K-group is G consecutive entries of
 // one table column block; four K-groups form a bundle, which one MFMA step consumes.
+//
+// Two forms:
+//  * direct (staged == false): meta[q] is the element offset of K-group q's input run
+//    relative to the output position, read straight from the padded input;
+//  * LDS-staged (staged == true): each tile's bundles are grouped into stage units
+//    (dy, chunk of CH inner entries).  A workgroup loads the input rows of its position patch
+//    shifted by dy, for the chunk and the unit's dx range, into LDS once, and then sweeps all
+//    (dx, G-run) K-groups of the unit from LDS; meta[q] is then the LDS element offset
+//    (dx + K) * CS + (run start - chunk start).
 struct Layout {
   int G = 0;
   int n_tiles = 0;          // output row tiles
   int out_len = 0;          // rows of the output vector (nt or nz)
   long long n_bundles = 0;
-  int* d_tile_start = nullptr;   // [n_tiles + 1] bundle range of each tile
-  int* d_meta = nullptr;         // [n_bundles * 4] input-element offset of each K-group
+  int* d_tile_start = nullptr;   // [n_tiles + 1] bundle range of each tile (direct form)
+  int* d_meta = nullptr;         // [n_bundles * 4] per K-group offset (see above)
   int4* d_groups = nullptr;      // [n_bundles * 4] (offset index, start, tile, active)
   std::vector<int> h_tile_start;
   long long mac_exec = 0;        // MACs issued per apply
   PadGeom in;                    // staged input geometry
+  // LDS-staged form
+  bool staged = false;
+  int CH = 0, BR = 0, BC = 0;    // chunk length, patch rows, patch columns
+  int CS = 0, NCOL = 0;          // LDS column stride (elements), staged columns BC + 2K
+  long long n_units = 0;
+  int* d_tile_units = nullptr;   // [n_tiles + 1] stage-unit range of each tile
+  int4* d_units = nullptr;       // [n_units] (dy, chunk start, bundle begin, bundle end)
+  int2* d_ucols = nullptr;       // [n_units] staged column range [c0, c1) of the patch window
+  size_t lds_bytes = 0;
 };
 
 struct Pack {
@@ -95,7 +115,9 @@ struct Model {
   int* d_colidx = nullptr;       // [n_off][nz]
   int* d_lo = nullptr;           // [n_columns]
   long long* d_off = nullptr;    // [n_columns + 1]
-  Layout fwd4, adj4, fwd8, adj8; // G = 4 (FP64/FP32) and G = 8 (BF16/FP8)
+  Layout g4f, g4a;               // direct form, G = 4: FP64 forward / adjoint
+  Layout s4f, s4a;               // LDS-staged, G = 4: FP32
+  Layout s8f, s8a;               // LDS-staged, G = 8: BF16 / FP8
   Pack fwd_pack[4], adj_pack[4]; // indexed by aroam_dtype
   unsigned dtype_mask = 0;
   size_t device_bytes = 0;

@@ -219,23 +219,53 @@ int alloc_copy(T** dst, const std::vector<T>& src, size_t& bytes) {
   return AROAM_OK;
 }
 
-PadGeom pad_geom(const aroam_grid& g, int L) {
+PadGeom pad_geom(const aroam_grid& g, int L, int BR = 1, int BC = 16, int CH = 0) {
   PadGeom p;
   p.K = g.k_half;
   p.nx = g.nx;
   p.ny = g.ny;
   p.ntx = (int)ceil_div(g.nx, 16);
-  p.nxp = 16 * p.ntx + 2 * p.K;
-  p.nyp = g.ny + 2 * p.K;
+  p.nxp = (int)round_up(g.nx, BC) + 2 * p.K;
+  p.nyp = (int)round_up(g.ny, BR) + 2 * p.K;
   p.L = L;
-  p.Lp = (int)round_up(L, 8) + 8;
+  p.Lp = CH > 0 ? (int)round_up(L, CH) : (int)round_up(L, 8) + 8;
   return p;
 }
 
-// Build the K-group lists of one operator.  For output tile t (rows 16t .. 16t+15) and each
-// offset, the K-groups are the G-aligned runs of the inner axis that intersect some column's
-// band inside the tile; runs with no band entry are skipped; each tile's list is padded with
-// empty groups to a multiple of four (one bundle = four groups).
+// Mark the G-aligned runs of the inner axis that meet some column's band inside output
+// tile t for offset oi (hit[q] = 1 for run q).  Returns whether any run was hit.
+bool tile_hits(const Model& m, bool adjoint, int G, int t, int oi, std::vector<char>& hit) {
+  const int nz = m.grid.nz;
+  const int out_len = adjoint ? nz : m.grid.nt;
+  const int r0 = kTile * t, r1 = std::min(out_len, r0 + kTile) - 1;
+  std::fill(hit.begin(), hit.end(), 0);
+  bool any = false;
+  if (!adjoint) {
+    for (int k = 0; k < nz; ++k) {
+      const int lo = m.h_lo[(size_t)oi * nz + k];
+      if (lo < 0) continue;
+      const int hi = m.h_hi[(size_t)oi * nz + k];
+      if (lo <= r1 && hi >= r0) {
+        hit[k / G] = 1;
+        any = true;
+      }
+    }
+  } else {
+    for (int k = r0; k <= r1; ++k) {
+      const int lo = m.h_lo[(size_t)oi * nz + k];
+      if (lo < 0) continue;
+      const int hi = m.h_hi[(size_t)oi * nz + k];
+      for (int q = lo / G; q <= hi / G; ++q) hit[q] = 1;
+      any = true;
+    }
+  }
+  return any;
+}
+
+// Build the K-group lists of one operator (direct form).  For output tile t (rows 16t ..
+// 16t+15) and each offset, the K-groups are the G-aligned runs of the inner axis that meet
+// some column's band inside the tile; runs with no band entry are skipped; each tile's list
+// is padded with empty groups to a multiple of four (one bundle = four groups).
 int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes) {
   const aroam_grid& g = m.grid;
   const int K = m.K, W = 2 * K + 1, nz = g.nz, nt = g.nt;
@@ -250,31 +280,9 @@ int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes
   std::vector<char> hit((size_t)ceil_div(inner, G) + 1);
   for (int t = 0; t < lay.n_tiles; ++t) {
     lay.h_tile_start[t] = (int)(groups.size() / kLaneGroups);
-    const int r0 = kTile * t, r1 = std::min(lay.out_len, r0 + kTile) - 1;
     for (int oi = 0; oi < m.n_off; ++oi) {
       const int dy = oi / W - K, dx = oi % W - K;
-      std::fill(hit.begin(), hit.end(), 0);
-      bool any = false;
-      if (!adjoint) {
-        for (int k = 0; k < nz; ++k) {
-          const int lo = m.h_lo[(size_t)oi * nz + k];
-          if (lo < 0) continue;
-          const int hi = m.h_hi[(size_t)oi * nz + k];
-          if (lo <= r1 && hi >= r0) {
-            hit[k / G] = 1;
-            any = true;
-          }
-        }
-      } else {
-        for (int k = r0; k <= r1; ++k) {
-          const int lo = m.h_lo[(size_t)oi * nz + k];
-          if (lo < 0) continue;
-          const int hi = m.h_hi[(size_t)oi * nz + k];
-          for (int q = lo / G; q <= hi / G; ++q) hit[q] = 1;
-          any = true;
-        }
-      }
-      if (!any) continue;
+      if (!tile_hits(m, adjoint, G, t, oi, hit)) continue;
       for (size_t q = 0; q < hit.size(); ++q) {
         if (!hit[q]) continue;
         const int start = (int)q * G;
@@ -298,6 +306,81 @@ int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes
   AROAM_TRY(alloc_copy(&lay.d_tile_start, lay.h_tile_start, bytes));
   AROAM_TRY(alloc_copy(&lay.d_meta, meta, bytes));
   AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
+  return AROAM_OK;
+}
+
+// LDS-staged form (see Layout).  For tile t and lateral row offset dy, the hit runs of all
+// dx are grouped by chunk (CH inner entries = CH / G runs); each non-empty (dy, chunk) is one
+// stage unit whose K-groups (dx, run) are packed four to a bundle.  A null K-group points at
+// the first staged column and multiplies zero table entries.
+int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int BC, int esize,
+                        Layout& lay, size_t& bytes) {
+  const aroam_grid& g = m.grid;
+  const int K = m.K, W = 2 * K + 1, nz = g.nz, nt = g.nt;
+  lay.G = G;
+  lay.staged = true;
+  lay.CH = CH;
+  lay.BR = BR;
+  lay.BC = BC;
+  lay.NCOL = BC + 2 * K;
+  lay.CS = CH + 16 / esize;  // 16 bytes of padding per column spread the LDS banks
+  lay.out_len = adjoint ? nz : nt;
+  lay.n_tiles = (int)ceil_div(lay.out_len, kTile);
+  lay.in = pad_geom(g, adjoint ? nt : nz, BR, BC, CH);
+  lay.lds_bytes = (size_t)BR * lay.NCOL * lay.CS * esize;
+  const int inner = adjoint ? nt : nz;
+  const int nq = (int)ceil_div(inner, G);
+  const int qpc = CH / G;  // runs per chunk
+  const int nch = (int)ceil_div(inner, CH);
+  std::vector<int4> groups, units;
+  std::vector<int2> ucols;
+  std::vector<int> meta, tile_units(lay.n_tiles + 1, 0);
+  std::vector<char> hit((size_t)nq + 1);
+  std::vector<std::vector<char>> hits(W, std::vector<char>((size_t)nq + 1));
+  std::vector<char> dx_any(W);
+  for (int t = 0; t < lay.n_tiles; ++t) {
+    tile_units[t] = (int)units.size();
+    for (int a = 0; a < W; ++a) {
+      const int dy = a - K;
+      for (int b = 0; b < W; ++b) dx_any[b] = tile_hits(m, adjoint, G, t, a * W + b, hits[b]);
+      for (int c = 0; c < nch; ++c) {
+        int dxmin = W, dxmax = -1;
+        const size_t first = groups.size();
+        for (int b = 0; b < W; ++b) {
+          if (!dx_any[b]) continue;
+          for (int q = c * qpc; q < std::min(nq, (c + 1) * qpc); ++q) {
+            if (!hits[b][q]) continue;
+            // the adjoint reads the input at position p - o, i.e. column offset -dx
+            const int col = adjoint ? (W - 1 - b) : b;
+            groups.push_back(make_int4(a * W + b, q * G, t, 1));
+            meta.push_back(col * lay.CS + (q * G - c * CH));
+            dxmin = std::min(dxmin, col);
+            dxmax = std::max(dxmax, col);
+          }
+        }
+        if (groups.size() == first) continue;
+        while ((groups.size() - first) % kLaneGroups) {
+          groups.push_back(make_int4(-1, 0, t, 0));
+          meta.push_back(dxmin * lay.CS);
+        }
+        const int b0 = (int)(first / kLaneGroups), b1 = (int)(groups.size() / kLaneGroups);
+        units.push_back(make_int4(adjoint ? -dy : dy, c * CH, b0, b1));
+        ucols.push_back(make_int2(dxmin, dxmax + BC));
+      }
+    }
+  }
+  tile_units[lay.n_tiles] = (int)units.size();
+  lay.n_units = (long long)units.size();
+  lay.n_bundles = (long long)groups.size() / kLaneGroups;
+  lay.mac_exec = lay.n_bundles * kLaneGroups * kTile * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
+  AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
+              "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
+  AROAM_TRY(alloc_copy(&lay.d_tile_units, tile_units, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_ucols, ucols, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_meta, meta, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
+  lay.h_tile_start = tile_units;
   return AROAM_OK;
 }
 
@@ -452,12 +535,14 @@ int build_impl(Model& m, hipStream_t st) {
   if (rc) return rc;
 
   // band tiles
-  AROAM_TRY(build_layout(m, false, 4, m.fwd4, bytes));
-  AROAM_TRY(build_layout(m, true, 4, m.adj4, bytes));
-  AROAM_TRY(pack_dtype<double>(m, m.fwd4, false, m.fwd_pack[AROAM_FP64], st, bytes));
-  AROAM_TRY(pack_dtype<double>(m, m.adj4, true, m.adj_pack[AROAM_FP64], st, bytes));
-  AROAM_TRY(pack_dtype<float>(m, m.fwd4, false, m.fwd_pack[AROAM_FP32], st, bytes));
-  AROAM_TRY(pack_dtype<float>(m, m.adj4, true, m.adj_pack[AROAM_FP32], st, bytes));
+  AROAM_TRY(build_layout(m, false, 4, m.g4f, bytes));
+  AROAM_TRY(build_layout(m, true, 4, m.g4a, bytes));
+  AROAM_TRY(pack_dtype<double>(m, m.g4f, false, m.fwd_pack[AROAM_FP64], st, bytes));
+  AROAM_TRY(pack_dtype<double>(m, m.g4a, true, m.adj_pack[AROAM_FP64], st, bytes));
+  AROAM_TRY(build_staged_layout(m, false, 4, 16, kPatchRows, kPatchCols, 4, m.s4f, bytes));
+  AROAM_TRY(build_staged_layout(m, true, 4, 16, kPatchRows, kPatchCols, 4, m.s4a, bytes));
+  AROAM_TRY(pack_dtype<float>(m, m.s4f, false, m.fwd_pack[AROAM_FP32], st, bytes));
+  AROAM_TRY(pack_dtype<float>(m, m.s4a, true, m.adj_pack[AROAM_FP32], st, bytes));
   m.dtype_mask = (1u << AROAM_FP64) | (1u << AROAM_FP32);
   return AROAM_OK;
 }
@@ -492,12 +577,12 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipSt
     const bool want8 = (mask & ((1u << AROAM_BF16) | (1u << AROAM_FP8E4M3))) != 0;
     size_t bytes = 0;
     if (want8) {
-      rc = build_layout(*m, false, 8, m->fwd8, bytes);
-      if (!rc) rc = build_layout(*m, true, 8, m->adj8, bytes);
+      rc = build_staged_layout(*m, false, 8, 32, kPatchRows, kPatchCols, 2, m->s8f, bytes);
+      if (!rc) rc = build_staged_layout(*m, true, 8, 32, kPatchRows, kPatchCols, 2, m->s8a, bytes);
     }
     if (!rc && (mask & (1u << AROAM_BF16))) {
-      rc = pack_dtype<uint16_t>(*m, m->fwd8, false, m->fwd_pack[AROAM_BF16], st, bytes);
-      if (!rc) rc = pack_dtype<uint16_t>(*m, m->adj8, true, m->adj_pack[AROAM_BF16], st, bytes);
+      rc = pack_dtype<uint16_t>(*m, m->s8f, false, m->fwd_pack[AROAM_BF16], st, bytes);
+      if (!rc) rc = pack_dtype<uint16_t>(*m, m->s8a, true, m->adj_pack[AROAM_BF16], st, bytes);
       if (!rc) m->dtype_mask |= 1u << AROAM_BF16;
     }
     if (!rc && hipStreamSynchronize(st) != hipSuccess) {
@@ -512,8 +597,9 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipSt
   // account device memory
   size_t b = (size_t)std::max<long long>(1, m->nnz) * sizeof(double);
   b += m->h_colidx.size() * sizeof(int) + m->n_columns * sizeof(int) + m->h_off.size() * 8;
-  for (const Layout* l : {&m->fwd4, &m->adj4, &m->fwd8, &m->adj8})
-    b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) + l->h_tile_start.size() * 4;
+  for (const Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a})
+    b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) + l->h_tile_start.size() * 4 +
+         l->n_units * (sizeof(int4) + sizeof(int2));
   for (int d = 0; d < 4; ++d) b += m->fwd_pack[d].bytes + m->adj_pack[d].bytes;
   m->device_bytes = b;
   *out = m;
@@ -526,10 +612,13 @@ void destroy_model(Model* m) {
   (void)hipFree(m->d_colidx);
   (void)hipFree(m->d_lo);
   (void)hipFree(m->d_off);
-  for (Layout* l : {&m->fwd4, &m->adj4, &m->fwd8, &m->adj8}) {
+  for (Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a}) {
     (void)hipFree(l->d_tile_start);
     (void)hipFree(l->d_meta);
     (void)hipFree(l->d_groups);
+    (void)hipFree(l->d_tile_units);
+    (void)hipFree(l->d_units);
+    (void)hipFree(l->d_ucols);
   }
   for (int d = 0; d < 4; ++d) {
     (void)hipFree(m->fwd_pack[d].d);
