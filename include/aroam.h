@@ -132,8 +132,10 @@ int aroam_adjoint(const aroam_model* model, int dtype, const void* s, void* x, v
  *                 (Tikhonov: 1e-2 ||A^T s||_2; L1: 5e-3 max|A^T s|) and reports it in info
  *   iters         iterations (fixed count, x0 = 0, no early stop)
  *   refine_sweeps LSQR: residual-correction sweeps after the first solve (0 = none)
- *   anchor_period FISTA: high-precision anchor gradient every this many iterations when
- *                 inner != outer (0 = 10)
+ *   anchor_period FISTA with inner != outer: after the warm-up, a high-precision anchor
+ *                 gradient every this many iterations (0 = 5)
+ *   anchor_warmup FISTA with inner != outer: the first this many iterations take the
+ *                 high-precision gradient at every iteration (< 0 = a quarter of iters)
  *   power_iters   FISTA: power-method iterations for the Lipschitz constant (0 = 50)
  *   lipschitz     FISTA: if > 0 use this L instead of the power method
  *   inner, outer  aroam_dtype of the iteration's applies and of the high-precision residuals
@@ -144,7 +146,7 @@ typedef struct {
   double lambda;
   int iters, refine_sweeps, anchor_period, power_iters;
   double lipschitz;
-  int inner, outer;
+  int inner, outer, anchor_warmup;
   const void* power_start;
 } aroam_solve_opts;
 

@@ -132,18 +132,20 @@ def fista(A, AT, s, lam, L, iters, x0=None, record=False):
 def lsqr_refined(A, AT, s, lam, iters, sweeps):
     """Residual-correction refinement schedule for Tikhonov LSQR.
 
-    x <- LSQR(s; damp = sqrt(lam)); then per sweep: residual of the stacked system
-    [A; sqrt(lam) I] x = [s; 0], i.e. r = (s - A x, -sqrt(lam) x); solve the correction
-    d <- LSQR([A; sqrt(lam) I], r; damp = 0) with the same iteration count; x <- x + d.
-    In the HIP path the corrections run at low precision and the residual at high
-    precision; here every step is FP64."""
+    x <- LSQR(s; damp = sqrt(lam)); then per sweep: the residual of the normal equations
+    g = A^T (s - A x) - lam x; the correction d solves (A^T A + lam I) d = g, written as the
+    least-squares problem  min || [A; sqrt(lam) I] d - [0; g / sqrt(lam)] ||  and solved by
+    LSQR (damp = 0) with the same iteration count; x <- x + d.  In the HIP path the
+    corrections run at low precision and g (both products) at high precision, so the fixed
+    point is the high-precision solution; here every step is FP64."""
     s = np.asarray(s, dtype=np.float64).ravel()
     damp = math.sqrt(lam)
     x, _ = lsqr(A, AT, s, damp=damp, iters=iters)
+    if sweeps > 0 and damp == 0.0:
+        raise ValueError("refinement needs lam > 0")
     m = s.size
     for _ in range(sweeps):
-        rs = s - A(x)
-        rx = -damp * x
+        g = AT(s - A(x)) - lam * x
 
         def As(v):
             return np.concatenate([A(v), damp * v])
@@ -151,16 +153,18 @@ def lsqr_refined(A, AT, s, lam, iters, sweeps):
         def ATs(u):
             return AT(u[:m]) + damp * u[m:]
 
-        d, _ = lsqr(As, ATs, np.concatenate([rs, rx]), damp=0.0, iters=iters)
+        rhs = np.concatenate([np.zeros(m), g / damp])
+        d, _ = lsqr(As, ATs, rhs, damp=0.0, iters=iters)
         x = x + d
     return x
 
 
-def fista_anchored(A, AT, s, lam, L, iters, period):
-    """Anchored-gradient schedule of FISTA: every `period` iterations an anchor gradient
-    g_a = 2 A^T (A x_a - s) is formed at high precision, and in between the gradient at y
-    is g_a + 2 A^T A (y - x_a) with low-precision products.  In exact arithmetic this is
-    plain FISTA; here (FP64) it is evaluated exactly as written."""
+def fista_anchored(A, AT, s, lam, L, iters, period, warmup=0):
+    """Anchored-gradient schedule of FISTA: during the first `warmup` iterations and then
+    every `period` iterations an anchor gradient g_a = 2 A^T (A x_a - s) is formed at high
+    precision (x_a = the current y), and in between the gradient at y is
+    g_a + 2 A^T A (y - x_a) with low-precision products.  In exact arithmetic this is plain
+    FISTA; here (FP64) it is evaluated exactly as written."""
     s = np.asarray(s, dtype=np.float64).ravel()
     n = AT(s).size
     x_prev = np.zeros(n)
@@ -168,7 +172,7 @@ def fista_anchored(A, AT, s, lam, L, iters, period):
     t = 1.0
     xa, ga = None, None
     for it in range(iters):
-        if it % period == 0:
+        if it < warmup or (it - warmup) % period == 0:
             xa = y.copy()
             ga = 2.0 * AT(A(xa) - s)
             g = ga

@@ -45,7 +45,8 @@ class ModelInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("iters", C.c_int), ("refine_sweeps", C.c_int),
                 ("anchor_period", C.c_int), ("power_iters", C.c_int), ("lipschitz", C.c_double),
-                ("inner", C.c_int), ("outer", C.c_int), ("power_start", C.c_void_p)]
+                ("inner", C.c_int), ("outer", C.c_int), ("anchor_warmup", C.c_int),
+                ("power_start", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -169,10 +170,11 @@ def aroam_adjoint(h, dtype, s, x, stream=None):
 
 
 def _opts(lam, iters, refine_sweeps=0, anchor_period=0, power_iters=0, lipschitz=0.0,
-          inner=AROAM_FP32, outer=None, power_start=None):
+          inner=AROAM_FP32, outer=None, anchor_warmup=-1, power_start=None):
     return SolveOpts(float(lam), int(iters), int(refine_sweeps), int(anchor_period),
                      int(power_iters), float(lipschitz), int(inner),
-                     int(inner if outer is None else outer), _ptr(power_start))
+                     int(inner if outer is None else outer), int(anchor_warmup),
+                     _ptr(power_start))
 
 
 def _info(i):
@@ -281,7 +283,8 @@ class Model:
         return out, info
 
     def solve_l1(self, s, lam=-1.0, iters=200, inner="fp32", outer=None, lipschitz=0.0,
-                 power_iters=50, anchor_period=10, power_start=None, out=None, stream=None):
+                 power_iters=50, anchor_period=0, anchor_warmup=-1, power_start=None, out=None,
+                 stream=None):
         import torch
         inner = DTYPES[inner] if isinstance(inner, str) else inner
         outer = inner if outer is None else (DTYPES[outer] if isinstance(outer, str) else outer)
@@ -293,8 +296,8 @@ class Model:
             _expect(power_start, self.image_shape, self._vec_dtype(inner))
         info = aroam_solve_l1(self.handle, s, out, stream, lam=lam, iters=iters,
                               lipschitz=lipschitz, power_iters=power_iters,
-                              anchor_period=anchor_period, inner=inner, outer=outer,
-                              power_start=power_start)
+                              anchor_period=anchor_period, anchor_warmup=anchor_warmup,
+                              inner=inner, outer=outer, power_start=power_start)
         return out, info
 
     def close(self):

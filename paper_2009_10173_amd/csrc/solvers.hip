@@ -273,18 +273,18 @@ __global__ void k_axpby(T* __restrict__ y, const T* __restrict__ a, const T* __r
 }
 
 template <typename T>
+__global__ void k_fill(T* __restrict__ y, double v, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) y[i] = (T)v;
+}
+
+template <typename T>
 __global__ void k_scale_dev(T* __restrict__ y, const T* __restrict__ a, const double* __restrict__ c,
                             long long n) {  // y = c[0] a
   const double cc = *c;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride)
     y[i] = (T)(cc * (double)a[i]);
-}
-
-template <typename T>
-__global__ void k_fill(T* __restrict__ y, double v, long long n) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) y[i] = (T)v;
 }
 
 struct FistaDev {
@@ -485,17 +485,22 @@ int lsqr_solve(const Model& m, const aroam_solve_opts& o, const T* s, T* x,
   if (status == AROAM_OK && o.refine_sweeps > 0) {
     const double lam = first.lambda;
     const double g = std::sqrt(lam);
-    T *rs, *rx, *dx;
+    AROAM_CHECK(g > 0, AROAM_EINVAL, "refinement sweeps need lambda > 0");
+    T *rs, *gx, *rx, *dx;
     AROAM_TRY(w.alloc(&rs, c.ns));
+    AROAM_TRY(w.alloc(&gx, c.nx));
     AROAM_TRY(w.alloc(&rx, c.nx));
     AROAM_TRY(w.alloc(&dx, c.nx));
     for (int sw = 0; sw < o.refine_sweeps; ++sw) {
-      // high-precision residual of the stacked system [A; sqrt(lam) I] x = [s; 0]
+      // high-precision residual of the normal equations: g = A^T (s - A x) - lam x.  The
+      // correction solves min || [A; sqrt(lam) I] d - [0; g / sqrt(lam)] || at low precision.
       AROAM_TRY(apply(m, false, outer, x, rs, c.stage_f, st));
       hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(c.ns)), dim3(256), 0, st, rs, s, (const T*)rs,
                          1.0, -1.0, c.ns);
-      hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(c.nx)), dim3(256), 0, st, rx, (const T*)x,
-                         (const T*)nullptr, -g, 0.0, c.nx);
+      AROAM_TRY(apply(m, true, outer, rs, gx, c.stage_a, st));
+      hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(c.nx)), dim3(256), 0, st, rx, (const T*)gx,
+                         (const T*)x, 1.0 / g, -g, c.nx);
+      hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(c.ns)), dim3(256), 0, st, rs, 0.0, c.ns);
       AROAM_HIP(hipGetLastError());
       AROAM_TRY(lsqr_run<T>(c, inner, o.iters, 0.0, g, 0, rs, rx, dx, d, w));
       hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(c.nx)), dim3(256), 0, st, x, (const T*)x,
@@ -533,7 +538,8 @@ int l1_solve(const Model& m, const aroam_solve_opts& o, const T* s, T* x, aroam_
   AROAM_TRY(check_dtype(m, outer));
   AROAM_CHECK(o.iters >= 0, AROAM_EINVAL, "negative iteration count");
   const int npow = o.power_iters > 0 ? o.power_iters : 50;
-  const int period = o.anchor_period > 0 ? o.anchor_period : 10;
+  const int period = o.anchor_period > 0 ? o.anchor_period : 5;
+  const int warmup = o.anchor_warmup >= 0 ? o.anchor_warmup : o.iters / 4;
   const bool anchored = inner != outer;
   Work<T> w;
   w.st = st;
@@ -603,7 +609,7 @@ int l1_solve(const Model& m, const aroam_solve_opts& o, const T* s, T* x, aroam_
       AROAM_TRY(apply(m, true, inner, ts, tx, c.stage_a, st));
       hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, st, y, xp, (const T*)nullptr,
                          (const T*)tx, mom, c.nx, (const FistaDev*)f);
-    } else if (it % period == 0) {
+    } else if (it < warmup || (it - warmup) % period == 0) {
       // anchor: exact gradient at y in the outer precision
       AROAM_HIP(hipMemcpyAsync(xa, y, c.nx * sizeof(T), hipMemcpyDeviceToDevice, st));
       AROAM_TRY(apply(m, false, outer, y, ts, c.stage_f, st));

@@ -41,7 +41,7 @@ def test_struct_layouts_match_header():
     # field order and C sizes of the public structs
     assert ctypes.sizeof(P.binding.Sensor) == 48
     assert ctypes.sizeof(P.binding.Grid) == 64
-    assert ctypes.sizeof(P.binding.SolveOpts) == 48
+    assert ctypes.sizeof(P.binding.SolveOpts) == 56
     assert ctypes.sizeof(P.binding.SolveInfo) == 48
 
 

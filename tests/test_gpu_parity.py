@@ -251,3 +251,43 @@ def test_bad_grid_is_rejected():
     with pytest.raises(P.AroamError) as e:
         P.Model(cfg["sensor"], g)
     assert e.value.status == -1
+
+
+# --- reduced precision with refinement ----------------------------------------------------
+
+@pytest.mark.parametrize("name", ["mid", "mid7"])
+def test_lsqr_bf16_refined_matches_oracle_schedule(name):
+    """BF16 applies inside LSQR, FP32 residuals, two correction sweeps; the reference is the
+    FP64 oracle running the identical schedule."""
+    m = gpu_model(name)
+    _, s = oracle_signals(name)
+    A, AT = oracle_ops(name)
+    iters, sweeps = 30, 2
+    lam = osol.lam_l2(AT(s.ravel()))
+    x_ref = osol.lsqr_refined(A, AT, s.ravel(), lam, iters, sweeps)
+    x, info = m.solve_lsqr(t32(s), lam=lam, iters=iters, inner="bf16", outer="fp32",
+                           refine_sweeps=sweeps)
+    x0, _ = m.solve_lsqr(t32(s), lam=lam, iters=iters, inner="bf16")
+    e_plain = rel_l2(x0.cpu().numpy(), x_ref)
+    e_ref = rel_l2(x.cpu().numpy(), x_ref)
+    print(f"[lsqr bf16 {name}] unrefined {e_plain:.2e} refined {e_ref:.2e}")
+    assert e_ref <= 1e-4
+    assert e_ref < e_plain
+
+
+@pytest.mark.parametrize("name,period,warmup", [("pairs16", 5, 50), ("mid7", 2, 15)])
+def test_fista_bf16_anchored_matches_oracle(name, period, warmup):
+    """BF16 correction applies with FP32 anchor gradients (every iteration during the
+    warm-up, then every `period`); in exact arithmetic the schedule is plain FISTA, so the
+    reference is the FP64 oracle's FISTA."""
+    m = gpu_model(name)
+    iters = 200 if name == "pairs16" else 60
+    s, L, lam, x_ref = _fista_ref(name, iters)
+    x, info = m.solve_l1(t32(s), lam=lam, iters=iters, inner="bf16", outer="fp32",
+                         lipschitz=L, anchor_period=period, anchor_warmup=warmup)
+    xb, _ = m.solve_l1(t32(s), lam=lam, iters=iters, inner="bf16", lipschitz=L)
+    e_a = rel_l2(x.cpu().numpy(), x_ref)
+    e_b = rel_l2(xb.cpu().numpy(), x_ref)
+    print(f"[fista bf16 {name}] plain bf16 {e_b:.2e} anchored {e_a:.2e}")
+    assert e_a < e_b
+    assert e_a <= 1e-4

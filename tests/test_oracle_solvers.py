@@ -144,8 +144,9 @@ def test_fista_anchored_equals_plain_in_fp64(tiny):
     L = solvers.lipschitz(sig2)
     lam = solvers.lam_l1(AT(s))
     x_plain, _ = solvers.fista(A, AT, s, lam, L, iters=40)
-    x_anch = solvers.fista_anchored(A, AT, s, lam, L, iters=40, period=10)
-    assert np.linalg.norm(x_anch - x_plain) <= 1e-10 * np.linalg.norm(x_plain)
+    for period, warmup in ((10, 0), (5, 12)):
+        x_anch = solvers.fista_anchored(A, AT, s, lam, L, iters=40, period=period, warmup=warmup)
+        assert np.linalg.norm(x_anch - x_plain) <= 1e-10 * np.linalg.norm(x_plain)
     assert np.count_nonzero(x_plain) < x_plain.size      # L1 gives a sparse image
 
 
