@@ -25,6 +25,7 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 
 
 template <typename Tin, typename Tout>
@@ -106,10 +107,12 @@ struct StagedArgs {
 // multiplies the 16 x (4 G) table block (from global memory, shared by the 4 waves through
 // L1) with the NT position tiles read from LDS.  Lane (n = lane % 16, g = lane / 16) holds
 // row n of K-group g of the table and the entries of K-group g for position n.
-template <typename T, int BR, int BC>
-__global__ __launch_bounds__(256) void k_apply_staged(const T* __restrict__ pack,
+template <typename T, int BR, int BC, bool FP8A>
+__global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ pack_raw,
+                                                      const float* __restrict__ gscale,
                                                       const T* __restrict__ in,
                                                       float* __restrict__ out, StagedArgs a) {
+  const T* pack = reinterpret_cast<const T*>(pack_raw);
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   constexpr int VEC = 16 / sizeof(T);  // entries per 16-byte vector == K-group width G
@@ -149,7 +152,29 @@ __global__ __launch_bounds__(256) void k_apply_staged(const T* __restrict__ pack
     __syncthreads();
     for (int b = U.z; b < U.w; ++b) {
       const int q = b * kLaneGroups + g;
-      const uint4 araw = *reinterpret_cast<const uint4*>(pack + ((long long)q * 16 + n) * VEC);
+      uint4 araw;
+      if constexpr (FP8A) {
+        // e4m3 table entries: decode 8 values, apply the K-group's scale, round to BF16
+        const uint2 r8 = *reinterpret_cast<const uint2*>(
+            reinterpret_cast<const uint8_t*>(pack_raw) + ((long long)q * 16 + n) * 8);
+        const float sc = gscale[q];
+        bf16x8 av;
+        const floatx2 f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.x, false);
+        const floatx2 f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.x, true);
+        const floatx2 f2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.y, false);
+        const floatx2 f3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.y, true);
+        av[0] = (__bf16)(f0.x * sc);
+        av[1] = (__bf16)(f0.y * sc);
+        av[2] = (__bf16)(f1.x * sc);
+        av[3] = (__bf16)(f1.y * sc);
+        av[4] = (__bf16)(f2.x * sc);
+        av[5] = (__bf16)(f2.y * sc);
+        av[6] = (__bf16)(f3.x * sc);
+        av[7] = (__bf16)(f3.y * sc);
+        araw = *reinterpret_cast<const uint4*>(&av);
+      } else {
+        araw = *reinterpret_cast<const uint4*>(pack + ((long long)q * 16 + n) * VEC);
+      }
       const int mo = a.meta[q];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -200,8 +225,7 @@ size_t elem_bytes(int dtype) {
   switch (dtype) {
     case AROAM_FP64: return 8;
     case AROAM_FP32: return 4;
-    case AROAM_BF16: return 2;
-    default: return 1;
+    default: return 2;  // BF16 and FP8 stage their vector operand as BF16
   }
 }
 
@@ -220,10 +244,10 @@ size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
 
 namespace {
 
-template <typename T>
+template <typename T, bool FP8A>
 int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out, hipStream_t st) {
   static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
-  auto kern = k_apply_staged<T, kPatchRows, kPatchCols>;
+  auto kern = k_apply_staged<T, kPatchRows, kPatchCols, FP8A>;
   static bool attr_set = false;  // allow the full LDS of a CU for wide footprints
   if (!attr_set) {
     AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -248,8 +272,8 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out,
   a.CS = lay.CS;
   a.CH = lay.CH;
   const dim3 grid((unsigned)(ceil_div(lay.in.ny, kPatchRows) * a.ncc), (unsigned)lay.n_tiles);
-  hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const T*)pk.d, (const T*)buf,
-                     (float*)out, a);
+  hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const void*)pk.d,
+                     (const float*)pk.d_scale, (const T*)buf, (float*)out, a);
   return AROAM_OK;
 }
 
@@ -261,7 +285,6 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
   AROAM_CHECK(in && out, AROAM_EINVAL, "NULL vector");
   AROAM_CHECK((m.dtype_mask >> dtype) & 1u, AROAM_EUNSUPPORTED,
               "model was not packed for dtype %d", dtype);
-  AROAM_CHECK(dtype != AROAM_FP8E4M3, AROAM_EUNSUPPORTED, "FP8 applies are not available");
   const Layout& lay = layout_for(m, adjoint, dtype);
   const Pack& pk = adjoint ? m.adj_pack[dtype] : m.fwd_pack[dtype];
   const PadGeom& pg = lay.in;
@@ -283,9 +306,11 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
     hipLaunchKernelGGL(k_apply_fma<double>, grid, dim3(256), 0, st, (const double*)pk.d,
                        (const double*)buf, (double*)out, a, lay.G);
   } else if (dtype == AROAM_FP32) {
-    AROAM_TRY(launch_staged<float>(lay, pk, buf, out, st));
+    AROAM_TRY((launch_staged<float, false>(lay, pk, buf, out, st)));
+  } else if (dtype == AROAM_BF16) {
+    AROAM_TRY((launch_staged<uint16_t, false>(lay, pk, buf, out, st)));
   } else {
-    AROAM_TRY(launch_staged<uint16_t>(lay, pk, buf, out, st));
+    AROAM_TRY((launch_staged<uint16_t, true>(lay, pk, buf, out, st)));
   }
   AROAM_HIP(hipGetLastError());
   if (!stage) AROAM_HIP(hipFreeAsync(buf, st));

@@ -210,6 +210,76 @@ __global__ void k_pack(long long total, int G, bool adjoint, const int4* __restr
   }
 }
 
+// FP8 e4m3 (OCP: bias 7, 3 mantissa bits, largest finite 448, no infinities), round to
+// nearest even, saturating at +-448.
+__device__ inline uint8_t f32_to_e4m3(float f) {
+  const uint8_t sign = (uint8_t)((__float_as_uint(f) >> 24) & 0x80u);
+  const float a = fabsf(f);
+  if (!(a == a)) return (uint8_t)(sign | 0x7f);
+  if (a >= 448.0f) return (uint8_t)(sign | 0x7e);
+  if (a < 0.015625f) {                     // subnormal range: multiples of 2^-9
+    const float q = rintf(a * 512.0f);     // q = 8 is the smallest normal, code 0x08
+    return (uint8_t)(sign | (uint8_t)q);
+  }
+  int e;
+  const float mant = frexpf(a, &e);        // a = mant 2^e, mant in [0.5, 1)
+  float q = rintf(mant * 16.0f);           // 8..16: implicit bit + 3 fraction bits
+  if (q >= 16.0f) {
+    q = 8.0f;
+    e += 1;
+  }
+  const int eb = e + 6;                    // a = (q / 8) 2^(e - 1), biased exponent e - 1 + 7
+  if (eb > 15 || (eb == 15 && q > 14.0f)) return (uint8_t)(sign | 0x7e);
+  return (uint8_t)(sign | (uint8_t)(eb << 3) | (uint8_t)((int)q - 8));
+}
+
+// Per (offset, 16-depth block) FP32 scale = amax / 448 of the block's table values.
+__global__ void k_block_scale(int n_off, int nz, const int* __restrict__ colidx,
+                              const long long* __restrict__ off, const double* __restrict__ band,
+                              float* __restrict__ scale) {
+  const int nblk = (nz + 15) / 16;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n_off * nblk) return;
+  const int oi = id / nblk, blk = id % nblk;
+  double amax = 0.0;
+  for (int k = 16 * blk; k < min(nz, 16 * blk + 16); ++k) {
+    const int c = colidx[(long long)oi * nz + k];
+    if (c < 0) continue;
+    for (long long i = off[c]; i < off[c + 1]; ++i) amax = fmax(amax, fabs(band[i]));
+  }
+  scale[id] = amax > 0.0 ? (float)(amax / 448.0) : 1.0f;
+}
+
+// FP8 pack: entries are e4m3(value / scale) with the scale of the entry's (offset, 16-depth
+// block); every K-group lies inside one block, so it carries one scale (gscale, 0 when empty).
+__global__ void k_pack_fp8(long long total, int G, bool adjoint, const int4* __restrict__ groups,
+                           int nz, int nt, const int* __restrict__ colidx,
+                           const int* __restrict__ lo, const long long* __restrict__ off,
+                           const double* __restrict__ band, const float* __restrict__ bscale,
+                           uint8_t* __restrict__ pack, float* __restrict__ gscale) {
+  const int nblk = (nz + 15) / 16;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long grp = idx / (16 * G);
+    const int m = (int)((idx / G) % 16);
+    const int j = (int)(idx % G);
+    const int4 gd = groups[grp];
+    const int kblk = adjoint ? gd.z : gd.y / 16;
+    const float sc = gd.x >= 0 ? bscale[(long long)gd.x * nblk + kblk] : 0.0f;
+    if (m == 0 && j == 0) gscale[grp] = sc;
+    int n, k;
+    if (!adjoint) {
+      n = 16 * gd.z + m;
+      k = gd.y + j;
+    } else {
+      k = 16 * gd.z + m;
+      n = gd.y + j;
+    }
+    const double v = table_value(gd.x, n, k, nz, nt, colidx, lo, off, band);
+    pack[idx] = sc > 0.0f ? f32_to_e4m3((float)(v / sc)) : (uint8_t)0;
+  }
+}
+
 template <typename T>
 int alloc_copy(T** dst, const std::vector<T>& src, size_t& bytes) {
   const size_t b = std::max<size_t>(1, src.size()) * sizeof(T);
@@ -401,6 +471,41 @@ int pack_dtype(const Model& m, const Layout& lay, bool adjoint, Pack& p, hipStre
   return AROAM_OK;
 }
 
+int pack_fp8(const Model& m, const Layout& lay, bool adjoint, const float* bscale, Pack& p,
+             hipStream_t st, size_t& bytes) {
+  const long long n_groups = lay.n_bundles * kLaneGroups;
+  const long long total = n_groups * kTile * lay.G;
+  p.bytes = std::max<long long>(1, total);
+  AROAM_HIP(hipMalloc(&p.d, p.bytes));
+  AROAM_HIP(hipMalloc((void**)&p.d_scale, std::max<long long>(1, n_groups) * sizeof(float)));
+  p.bytes += std::max<long long>(1, n_groups) * sizeof(float);
+  bytes += p.bytes;
+  if (total > 0) {
+    const int blocks = (int)std::min<long long>(ceil_div(total, 256), 1 << 16);
+    hipLaunchKernelGGL(k_pack_fp8, dim3(blocks), dim3(256), 0, st, total, lay.G, adjoint,
+                       lay.d_groups, m.grid.nz, m.grid.nt, m.d_colidx, m.d_lo, m.d_off, m.d_band,
+                       bscale, (uint8_t*)p.d, p.d_scale);
+    AROAM_HIP(hipGetLastError());
+  }
+  return AROAM_OK;
+}
+
+int pack_all_fp8(Model& m, hipStream_t st, size_t& bytes) {
+  const int nblk = (int)ceil_div(m.grid.nz, 16);
+  float* bscale = nullptr;
+  const long long nb = (long long)m.n_off * nblk;
+  AROAM_HIP(hipMalloc((void**)&bscale, std::max<long long>(1, nb) * sizeof(float)));
+  hipLaunchKernelGGL(k_block_scale, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, st, m.n_off,
+                     m.grid.nz, m.d_colidx, m.d_off, m.d_band, bscale);
+  int rc = hipGetLastError() == hipSuccess ? AROAM_OK : AROAM_EDEVICE;
+  if (!rc) rc = pack_fp8(m, m.s8f, false, bscale, m.fwd_pack[AROAM_FP8E4M3], st, bytes);
+  if (!rc) rc = pack_fp8(m, m.s8a, true, bscale, m.adj_pack[AROAM_FP8E4M3], st, bytes);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = AROAM_EDEVICE;
+  (void)hipFree(bscale);
+  if (rc) set_error("FP8 packing failed");
+  return rc;
+}
+
 int build_impl(Model& m, hipStream_t st) {
   const aroam_sensor& s = m.sensor;
   const aroam_grid& g = m.grid;
@@ -584,6 +689,10 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipSt
       rc = pack_dtype<uint16_t>(*m, m->s8f, false, m->fwd_pack[AROAM_BF16], st, bytes);
       if (!rc) rc = pack_dtype<uint16_t>(*m, m->s8a, true, m->adj_pack[AROAM_BF16], st, bytes);
       if (!rc) m->dtype_mask |= 1u << AROAM_BF16;
+    }
+    if (!rc && (mask & (1u << AROAM_FP8E4M3))) {
+      rc = pack_all_fp8(*m, st, bytes);
+      if (!rc) m->dtype_mask |= 1u << AROAM_FP8E4M3;
     }
     if (!rc && hipStreamSynchronize(st) != hipSuccess) {
       set_error("model packing failed");

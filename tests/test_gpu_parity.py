@@ -29,7 +29,7 @@ def _dev():
 _MODELS = {}
 
 
-def gpu_model(name, dtypes=("fp64", "fp32", "bf16")):
+def gpu_model(name, dtypes=("fp64", "fp32", "bf16", "fp8")):
     key = (name, tuple(dtypes))
     if key not in _MODELS:
         cfg = W.config(name)
@@ -291,3 +291,37 @@ def test_fista_bf16_anchored_matches_oracle(name, period, warmup):
     print(f"[fista bf16 {name}] plain bf16 {e_b:.2e} anchored {e_a:.2e}")
     assert e_a < e_b
     assert e_a <= 1e-4
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_forward_adjoint_fp8_reported(name):
+    """e4m3 table with one FP32 scale per (offset, 16-depth block), BF16 vector operands, FP32
+    accumulation: error vs the FP64 oracle is reported.  e4m3 keeps 3 mantissa bits, so an
+    entry carries up to 2^-4 = 6.25 % rounding error (entries far below their block's maximum
+    fall into the subnormal range and carry more); the bound is 1e-1."""
+    cfg = W.config(name)
+    m = gpu_model(name)
+    H = oracle_table(name)
+    x0, _ = oracle_signals(name)
+    y = W.random_signal(cfg, 13)
+    e_f = rel_l2(m.forward(t32(x0), "fp8").cpu().numpy(), oops.forward(H, x0))
+    e_a = rel_l2(m.adjoint(t32(y), "fp8").cpu().numpy(), oops.adjoint(H, y))
+    print(f"[fp8 {name}] forward rel L2 {e_f:.2e} adjoint rel L2 {e_a:.2e}")
+    assert e_f <= 1e-1 and e_a <= 1e-1
+
+
+@pytest.mark.parametrize("name,sweeps", [("mid", 3), ("mid7", 3)])
+def test_lsqr_fp8_refined_matches_oracle_schedule(name, sweeps):
+    m = gpu_model(name)
+    _, s = oracle_signals(name)
+    A, AT = oracle_ops(name)
+    iters = 30
+    lam = osol.lam_l2(AT(s.ravel()))
+    x_ref = osol.lsqr_refined(A, AT, s.ravel(), lam, iters, sweeps)
+    x, info = m.solve_lsqr(t32(s), lam=lam, iters=iters, inner="fp8", outer="fp32",
+                           refine_sweeps=sweeps)
+    x0, _ = m.solve_lsqr(t32(s), lam=lam, iters=iters, inner="fp8")
+    e_plain = rel_l2(x0.cpu().numpy(), x_ref)
+    e_ref = rel_l2(x.cpu().numpy(), x_ref)
+    print(f"[lsqr fp8 {name}] unrefined {e_plain:.2e} refined ({sweeps} sweeps) {e_ref:.2e}")
+    assert e_ref <= 1e-4 and e_ref < e_plain
