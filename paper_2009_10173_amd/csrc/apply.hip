@@ -92,104 +92,185 @@ __global__ __launch_bounds__(256) void k_apply_fma(const T* __restrict__ pack, c
 
 struct StagedArgs {
   const int* tile_units;
-  const int4* units;
-  const int2* ucols;
+  const int4* units;  // (row offset, chunk start, bundle begin, bundle end)
+  const int2* urows;  // padded patch rows [lo, hi) each unit loads into the LDS ring
   const int* meta;
   int out_len, nx, ny, K, nxp, Lp;
-  int ncc;         // patch column chunks
-  int NCOL, CS, CH;
+  int ncc;            // patch column chunks
+  int NCOL, CS;
 };
+
+// Table operand of one bundle for one lane: 16 bytes (FP32 / BF16) or 8 bytes of e4m3 plus
+// the K-group's scale.
+template <typename T, bool FP8A>
+struct AFrag {
+  uint4 v;
+  float sc;
+  int mo;
+};
+
+template <typename T, bool FP8A>
+__device__ inline void load_a(const void* __restrict__ pack_raw, const float* __restrict__ gscale,
+                              const int* __restrict__ meta, int b, int g, int n,
+                              AFrag<T, FP8A>& f) {
+  const int q = b * kLaneGroups + g;
+  if constexpr (FP8A) {
+    const uint2 r8 = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(pack_raw) +
+                                                     ((long long)q * 16 + n) * 8);
+    f.v = make_uint4(r8.x, r8.y, 0u, 0u);
+    f.sc = gscale[q];
+  } else {
+    constexpr int VEC = 16 / sizeof(T);
+    f.v = *reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(pack_raw) +
+                                          ((long long)q * 16 + n) * VEC);
+    f.sc = 1.0f;
+  }
+  f.mo = meta[q];
+}
+
+// e4m3 entries of a fragment -> BF16 operand with the K-group's scale applied.
+__device__ inline uint4 decode_fp8(const uint4& v, float sc) {
+  bf16x8 av;
+  const floatx2 f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, false);
+  const floatx2 f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, true);
+  const floatx2 f2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.y, false);
+  const floatx2 f3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.y, true);
+  av[0] = (__bf16)(f0.x * sc);
+  av[1] = (__bf16)(f0.y * sc);
+  av[2] = (__bf16)(f1.x * sc);
+  av[3] = (__bf16)(f1.y * sc);
+  av[4] = (__bf16)(f2.x * sc);
+  av[5] = (__bf16)(f2.y * sc);
+  av[6] = (__bf16)(f3.x * sc);
+  av[7] = (__bf16)(f3.y * sc);
+  return *reinterpret_cast<const uint4*>(&av);
+}
 
 // LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 rows) and one patch
 // of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT 16-position
-// tiles.  Per stage unit (dy, chunk) the patch's input rows shifted by dy, the unit's column
-// window and the chunk's CH inner entries are copied to LDS; then every bundle of the unit
-// multiplies the 16 x (4 G) table block (from global memory, shared by the 4 waves through
-// L1) with the NT position tiles read from LDS.  Lane (n = lane % 16, g = lane / 16) holds
-// row n of K-group g of the table and the entries of K-group g for position n.
+// tiles.  The tile's bundles are grouped into stage units (chunk, input row offset).  The LDS
+// holds BR input rows (all BC + 2K columns, the chunk's CH inner entries) as a ring indexed by
+// padded row modulo BR: a unit loads only the rows it adds to the ring, and those rows are
+// fetched into registers while the previous unit computes.  Table fragments stream through a
+// PD-deep register ring that runs across unit boundaries.  Lane (n = lane % 16,
+// g = lane / 16) holds row n of K-group g of the table and the entries of K-group g for
+// position n.
 template <typename T, int BR, int BC, bool FP8A>
 __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ pack_raw,
                                                       const float* __restrict__ gscale,
                                                       const T* __restrict__ in,
                                                       float* __restrict__ out, StagedArgs a) {
-  const T* pack = reinterpret_cast<const T*>(pack_raw);
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   constexpr int VEC = 16 / sizeof(T);  // entries per 16-byte vector == K-group width G
   constexpr int TPR = BC / 16;
   constexpr int RW = BR / 4;
   constexpr int NT = RW * TPR;
+  constexpr int PF = 2;                // prefetched stage vectors per thread
+  constexpr int PD = 4;                // table-fragment ring depth
+  constexpr int CH = 4 * VEC;          // chunk = one bundle's four K-groups... per lane group
   const int tile = blockIdx.y;
   const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int n = lane % 16, g = lane / 16;
-  int lbase[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
-    lbase[t] = (r * a.NCOL + c) * a.CS;
-  }
+  constexpr int nvec = CH / VEC;       // 16-byte vectors per staged column
+  const int rowvec = a.NCOL * nvec;    // 16-byte vectors per staged row
   floatx4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int u0 = a.tile_units[tile], u1 = a.tile_units[tile + 1];
-  const int nvec = a.CH / VEC;
-  for (int u = u0; u < u1; ++u) {
-    const int4 U = a.units[u];   // (row offset, chunk start, bundle begin, bundle end)
-    const int2 C = a.ucols[u];   // staged columns [C.x, C.y)
-    const int ncols = C.y - C.x;
-    const int total = BR * ncols * nvec;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < total; idx += 256) {
-      const int v = idx % nvec;
-      const int rc = idx / nvec;
-      const int c = C.x + rc % ncols, r = rc / ncols;
-      const long long src =
-          ((long long)(py0 + r + U.x + a.K) * a.nxp + (px0 + c)) * a.Lp + U.y + v * VEC;
-      *reinterpret_cast<uint4*>(lds + (r * a.NCOL + c) * a.CS + v * VEC) =
-          *reinterpret_cast<const uint4*>(in + src);
-    }
-    __syncthreads();
-    for (int b = U.z; b < U.w; ++b) {
-      const int q = b * kLaneGroups + g;
-      uint4 araw;
-      if constexpr (FP8A) {
-        // e4m3 table entries: decode 8 values, apply the K-group's scale, round to BF16
-        const uint2 r8 = *reinterpret_cast<const uint2*>(
-            reinterpret_cast<const uint8_t*>(pack_raw) + ((long long)q * 16 + n) * 8);
-        const float sc = gscale[q];
-        bf16x8 av;
-        const floatx2 f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.x, false);
-        const floatx2 f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.x, true);
-        const floatx2 f2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.y, false);
-        const floatx2 f3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r8.y, true);
-        av[0] = (__bf16)(f0.x * sc);
-        av[1] = (__bf16)(f0.y * sc);
-        av[2] = (__bf16)(f1.x * sc);
-        av[3] = (__bf16)(f1.y * sc);
-        av[4] = (__bf16)(f2.x * sc);
-        av[5] = (__bf16)(f2.y * sc);
-        av[6] = (__bf16)(f3.x * sc);
-        av[7] = (__bf16)(f3.y * sc);
-        araw = *reinterpret_cast<const uint4*>(&av);
-      } else {
-        araw = *reinterpret_cast<const uint4*>(pack + ((long long)q * 16 + n) * VEC);
+  if (u0 < u1) {
+    // stage-vector address of flat index idx of unit (rows [lo, hi)), chunk start e0
+    auto src_of = [&](int lo, int e0, int idx, int& lds_off) -> long long {
+      const int G = lo + idx / rowvec;
+      const int rem = idx % rowvec;
+      const int c = rem / nvec, v = rem % nvec;
+      lds_off = ((G % BR) * a.NCOL + c) * a.CS + v * VEC;
+      return ((long long)(py0 + G) * a.nxp + (px0 + c)) * a.Lp + e0 + v * VEC;
+    };
+    uint4 pf[PF];
+    int pf_off[PF];
+    auto prefetch = [&](int u) {
+      const int4 U = a.units[u];
+      const int2 Rr = a.urows[u];
+      const int nv = (Rr.y - Rr.x) * rowvec;
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        const int idx = threadIdx.x + 256 * i;
+        pf_off[i] = -1;
+        if (idx < nv) {
+          const long long src = src_of(Rr.x, U.y, idx, pf_off[i]);
+          pf[i] = *reinterpret_cast<const uint4*>(in + src);
+        }
       }
-      const int mo = a.meta[q];
+    };
+    prefetch(u0);
+    // table-fragment ring over the tile's whole bundle range
+    const int B1 = a.units[u1 - 1].w;
+    int bnext = a.units[u0].z;
+    AFrag<T, FP8A> ring[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+      if (bnext < B1) load_a<T, FP8A>(pack_raw, gscale, a.meta, bnext, g, n, ring[j]);
+      ++bnext;
+    }
+    for (int u = u0; u < u1; ++u) {
+      const int4 U = a.units[u];
+      const int2 Rr = a.urows[u];
+      __syncthreads();  // every wave is done reading the rows this unit replaces
+#pragma unroll
+      for (int i = 0; i < PF; ++i)
+        if (pf_off[i] >= 0) *reinterpret_cast<uint4*>(lds + pf_off[i]) = pf[i];
+      const int nv = (Rr.y - Rr.x) * rowvec;
+      for (int base = 256 * PF; base < nv; base += 256 * 8) {  // rows beyond the prefetch
+        uint4 tmp[8];
+        int off[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int idx = base + threadIdx.x + 256 * i;
+          off[i] = -1;
+          if (idx < nv) tmp[i] = *reinterpret_cast<const uint4*>(in + src_of(Rr.x, U.y, idx, off[i]));
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (off[i] >= 0) *reinterpret_cast<uint4*>(lds + off[i]) = tmp[i];
+      }
+      __syncthreads();
+      if (u + 1 < u1) prefetch(u + 1);
+      // LDS base of this lane's positions for the unit's row offset
+      const int R = U.x + a.K;
+      int lbase[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const uint4 xraw = *reinterpret_cast<const uint4*>(lds + lbase[t] + mo);
-        if constexpr (sizeof(T) == 4) {
-          const float4 av = *reinterpret_cast<const float4*>(&araw);
-          const float4 xv = *reinterpret_cast<const float4*>(&xraw);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[t], 0, 0, 0);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[t], 0, 0, 0);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[t], 0, 0, 0);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[t], 0, 0, 0);
-        } else {
-          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&araw);
-          const bf16x8 xv = *reinterpret_cast<const bf16x8*>(&xraw);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[t], 0, 0, 0);
+        const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
+        lbase[t] = (((r + R) % BR) * a.NCOL + c) * a.CS;
+      }
+      for (int b = U.z; b < U.w; ++b) {
+        const AFrag<T, FP8A> cur = ring[0];
+#pragma unroll
+        for (int j = 0; j + 1 < PD; ++j) ring[j] = ring[j + 1];
+        if (bnext < B1) load_a<T, FP8A>(pack_raw, gscale, a.meta, bnext, g, n, ring[PD - 1]);
+        ++bnext;
+        uint4 araw;
+        if constexpr (FP8A) araw = decode_fp8(cur.v, cur.sc);
+        else araw = cur.v;
+        uint4 xraw[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) xraw[t] = *reinterpret_cast<const uint4*>(lds + lbase[t] + cur.mo);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if constexpr (sizeof(T) == 4) {
+            const float4 av = *reinterpret_cast<const float4*>(&araw);
+            const float4 xv = *reinterpret_cast<const float4*>(&xraw[t]);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[t], 0, 0, 0);
+          } else {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&araw);
+            const bf16x8 xv = *reinterpret_cast<const bf16x8*>(&xraw[t]);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[t], 0, 0, 0);
+          }
         }
       }
     }
@@ -259,7 +340,7 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out,
   StagedArgs a;
   a.tile_units = lay.d_tile_units;
   a.units = lay.d_units;
-  a.ucols = lay.d_ucols;
+  a.urows = lay.d_ucols;
   a.meta = lay.d_meta;
   a.out_len = lay.out_len;
   a.nx = lay.in.nx;
@@ -270,7 +351,7 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out,
   a.ncc = (int)ceil_div(lay.in.nx, kPatchCols);
   a.NCOL = lay.NCOL;
   a.CS = lay.CS;
-  a.CH = lay.CH;
+  AROAM_CHECK(lay.CH == 4 * (int)(16 / sizeof(T)), AROAM_EINVAL, "chunk length mismatch");
   const dim3 grid((unsigned)(ceil_div(lay.in.ny, kPatchRows) * a.ncc), (unsigned)lay.n_tiles);
   hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const void*)pk.d,
                      (const float*)pk.d_scale, (const T*)buf, (float*)out, a);

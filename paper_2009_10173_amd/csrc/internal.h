@@ -88,7 +88,7 @@ struct Layout {
   long long n_units = 0;
   int* d_tile_units = nullptr;   // [n_tiles + 1] stage-unit range of each tile
   int4* d_units = nullptr;       // [n_units] (dy, chunk start, bundle begin, bundle end)
-  int2* d_ucols = nullptr;       // [n_units] staged column range [c0, c1) of the patch window
+  int2* d_ucols = nullptr;       // [n_units] padded input rows [lo, hi) the unit loads (ring)
   size_t lds_bytes = 0;
 };
 

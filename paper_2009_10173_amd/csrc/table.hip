@@ -379,10 +379,14 @@ int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes
   return AROAM_OK;
 }
 
-// LDS-staged form (see Layout).  For tile t and lateral row offset dy, the hit runs of all
-// dx are grouped by chunk (CH inner entries = CH / G runs); each non-empty (dy, chunk) is one
-// stage unit whose K-groups (dx, run) are packed four to a bundle.  A null K-group points at
-// the first staged column and multiplies zero table entries.
+// LDS-staged form (see Layout).  For tile t, the hit runs of every lateral offset are
+// grouped by chunk (CH inner entries = CH / G runs) and by input row offset; each non-empty
+// (chunk, row offset) is one stage unit whose K-groups (dx, run) are packed four to a
+// bundle.  Units are ordered by chunk, then by ascending row offset, so that the LDS rows
+// form a ring: a unit only loads the input rows that the previous unit of the same chunk did
+// not hold (one row when the offset steps by one).  The row range to load is stored per unit
+// as [lo, hi) in patch-relative padded rows G = row offset + K + r.  A null K-group reads
+// staged column 0 and multiplies zero table entries.
 int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int BC, int esize,
                         Layout& lay, size_t& bytes) {
   const aroam_grid& g = m.grid;
@@ -403,39 +407,49 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int
   const int qpc = CH / G;  // runs per chunk
   const int nch = (int)ceil_div(inner, CH);
   std::vector<int4> groups, units;
-  std::vector<int2> ucols;
+  std::vector<int2> urows;
   std::vector<int> meta, tile_units(lay.n_tiles + 1, 0);
-  std::vector<char> hit((size_t)nq + 1);
   std::vector<std::vector<char>> hits(W, std::vector<char>((size_t)nq + 1));
   std::vector<char> dx_any(W);
+  // per (chunk, row-offset slot) list of (group, meta) of the current tile
+  std::vector<std::vector<std::pair<int4, int>>> per((size_t)nch * W);
   for (int t = 0; t < lay.n_tiles; ++t) {
     tile_units[t] = (int)units.size();
+    for (auto& v : per) v.clear();
     for (int a = 0; a < W; ++a) {
-      const int dy = a - K;
+      // input row offset: +dy for the forward, -dy for the adjoint; slot = offset + K
+      const int slot = adjoint ? (W - 1 - a) : a;
       for (int b = 0; b < W; ++b) dx_any[b] = tile_hits(m, adjoint, G, t, a * W + b, hits[b]);
-      for (int c = 0; c < nch; ++c) {
-        int dxmin = W, dxmax = -1;
-        const size_t first = groups.size();
-        for (int b = 0; b < W; ++b) {
-          if (!dx_any[b]) continue;
-          for (int q = c * qpc; q < std::min(nq, (c + 1) * qpc); ++q) {
-            if (!hits[b][q]) continue;
-            // the adjoint reads the input at position p - o, i.e. column offset -dx
-            const int col = adjoint ? (W - 1 - b) : b;
-            groups.push_back(make_int4(a * W + b, q * G, t, 1));
-            meta.push_back(col * lay.CS + (q * G - c * CH));
-            dxmin = std::min(dxmin, col);
-            dxmax = std::max(dxmax, col);
-          }
+      for (int b = 0; b < W; ++b) {
+        if (!dx_any[b]) continue;
+        const int col = adjoint ? (W - 1 - b) : b;  // input column offset + K
+        for (int q = 0; q < nq; ++q) {
+          if (!hits[b][q]) continue;
+          const int c = q / qpc;
+          per[(size_t)c * W + slot].push_back(
+              std::make_pair(make_int4(a * W + b, q * G, t, 1), col * lay.CS + (q * G - c * CH)));
         }
-        if (groups.size() == first) continue;
+      }
+    }
+    for (int c = 0; c < nch; ++c) {
+      int prevR = -1;
+      for (int R = 0; R < W; ++R) {
+        auto& lst = per[(size_t)c * W + R];
+        if (lst.empty()) continue;
+        const size_t first = groups.size();
+        for (auto& e : lst) {
+          groups.push_back(e.first);
+          meta.push_back(e.second);
+        }
         while ((groups.size() - first) % kLaneGroups) {
           groups.push_back(make_int4(-1, 0, t, 0));
-          meta.push_back(dxmin * lay.CS);
+          meta.push_back(0);
         }
-        const int b0 = (int)(first / kLaneGroups), b1 = (int)(groups.size() / kLaneGroups);
-        units.push_back(make_int4(adjoint ? -dy : dy, c * CH, b0, b1));
-        ucols.push_back(make_int2(dxmin, dxmax + BC));
+        const int lo = (prevR < 0 || R >= prevR + BR) ? R : prevR + BR;
+        units.push_back(make_int4(R - K, c * CH, (int)(first / kLaneGroups),
+                                  (int)(groups.size() / kLaneGroups)));
+        urows.push_back(make_int2(lo, R + BR));
+        prevR = R;
       }
     }
   }
@@ -447,7 +461,7 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int
               "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
   AROAM_TRY(alloc_copy(&lay.d_tile_units, tile_units, bytes));
   AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
-  AROAM_TRY(alloc_copy(&lay.d_ucols, ucols, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_ucols, urows, bytes));
   AROAM_TRY(alloc_copy(&lay.d_meta, meta, bytes));
   AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
   lay.h_tile_start = tile_units;
