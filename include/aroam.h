@@ -181,6 +181,39 @@ int aroam_forward_batch(int n, const aroam_model* const* models, int dtype,
 int aroam_adjoint_batch(int n, const aroam_model* const* models, int dtype,
                         const float* const* s, float* const* x, void* stream);
 
+/* Device bytes a solve allocates for its work vectors, stage buffers and FP64 state (what
+ * the request scheduler charges against its budget; the model's tables are not included).
+ * kind: 0 = LSQR (aroam_solve_lsqr), 1 = FISTA (aroam_solve_l1). */
+int aroam_solve_footprint(const aroam_model* model, int kind, const aroam_solve_opts* opts,
+                          size_t* bytes);
+
+/* Continuous-batching request scheduler (a serving loop around the two solvers).
+ * A request is one reconstruction: a model (device-resident, shared by requests), a solver
+ * kind (0 = LSQR, 1 = FISTA), options, and caller-owned DEVICE vectors s (signals) and x
+ * (result), which must stay valid until the request is collected.  Requests are admitted in
+ * submission order while one of `max_slots` streams is free and the sum of the resident
+ * requests' aroam_solve_footprint stays within `hbm_budget_bytes`; a request whose footprint
+ * alone exceeds the budget is finished with status AROAM_ENOMEM.  Each aroam_server_poll
+ * call retires completed requests, admits waiting ones, and enqueues `tick_iters` more
+ * iterations of every resident request on its own stream, so resident requests run
+ * concurrently on the device; it does not block.  A request's kernels and their order do not
+ * depend on the other requests, so each result is the same alone and in a mix.
+ * Streams are created at the default priority.  All calls on one server must come from one
+ * host thread.  aroam_server_destroy waits for resident work and releases everything. */
+typedef struct aroam_server aroam_server;
+int aroam_server_create(size_t hbm_budget_bytes, int max_slots, int tick_iters,
+                        aroam_server** out);
+/* Queue a request; *id (may be NULL) receives its identifier (1, 2, ...). */
+int aroam_server_submit(aroam_server* server, const aroam_model* model, int kind,
+                        const aroam_solve_opts* opts, const void* s, void* x, long long* id);
+/* One scheduling round; reports the resident and queued request counts (either may be NULL). */
+int aroam_server_poll(aroam_server* server, int* n_resident, int* n_queued);
+/* Up to `max` finished requests, oldest first: ids[i], infos[i] (infos may be NULL; status
+ * AROAM_OK, AROAM_ENONFINITE or AROAM_ENOMEM).  *n receives the count. */
+int aroam_server_collect(aroam_server* server, int max, long long* ids, aroam_solve_info* infos,
+                         int* n);
+void aroam_server_destroy(aroam_server* server);
+
 /* Release a model and its device memory (NULL is ignored). */
 void aroam_model_destroy(aroam_model* model);
 

@@ -72,6 +72,15 @@ _SYMBOLS = {
     "aroam_adjoint_batch": ([C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
                             C.c_int),
     "aroam_model_destroy": ([C.c_void_p], None),
+    "aroam_solve_footprint": ([C.c_void_p, C.c_int, C.POINTER(SolveOpts),
+                               C.POINTER(C.c_size_t)], C.c_int),
+    "aroam_server_create": ([C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "aroam_server_submit": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(SolveOpts), C.c_void_p,
+                             C.c_void_p, C.POINTER(C.c_longlong)], C.c_int),
+    "aroam_server_poll": ([C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "aroam_server_collect": ([C.c_void_p, C.c_int, C.POINTER(C.c_longlong),
+                              C.POINTER(SolveInfo), C.POINTER(C.c_int)], C.c_int),
+    "aroam_server_destroy": ([C.c_void_p], None),
     "aroam_last_error": ([], C.c_char_p),
 }
 
@@ -215,6 +224,47 @@ def aroam_adjoint_batch(hs, dtype, ss, xs, stream=None):
 def aroam_model_destroy(h):
     if h is not None and h.value:
         load_library().aroam_model_destroy(h)
+
+
+def aroam_solve_footprint(h, kind, **opts):
+    b = C.c_size_t()
+    _check(load_library().aroam_solve_footprint(h, int(kind), C.byref(_opts(**opts)), C.byref(b)))
+    return b.value
+
+
+def aroam_server_create(hbm_budget_bytes, max_slots=8, tick_iters=2):
+    h = C.c_void_p()
+    _check(load_library().aroam_server_create(int(hbm_budget_bytes), int(max_slots),
+                                              int(tick_iters), C.byref(h)))
+    return h
+
+
+def aroam_server_submit(server, model_h, kind, s, x, **opts):
+    """Queue one reconstruction (kind 0 = LSQR, 1 = FISTA); s and x must stay alive until the
+    request is collected.  Returns the request id."""
+    rid = C.c_longlong()
+    _check(load_library().aroam_server_submit(server, model_h, int(kind), C.byref(_opts(**opts)),
+                                              _ptr(s), _ptr(x), C.byref(rid)))
+    return rid.value
+
+
+def aroam_server_poll(server):
+    nr, nq = C.c_int(), C.c_int()
+    _check(load_library().aroam_server_poll(server, C.byref(nr), C.byref(nq)))
+    return nr.value, nq.value
+
+
+def aroam_server_collect(server, max_n=256):
+    ids = (C.c_longlong * max_n)()
+    infos = (SolveInfo * max_n)()
+    n = C.c_int()
+    _check(load_library().aroam_server_collect(server, max_n, ids, infos, C.byref(n)))
+    return [(ids[i], _info(infos[i])) for i in range(n.value)]
+
+
+def aroam_server_destroy(server):
+    if server is not None and server.value:
+        load_library().aroam_server_destroy(server)
 
 
 # --- convenience wrapper -----------------------------------------------------------------

@@ -172,6 +172,76 @@ int aroam_adjoint_batch(int n, const aroam_model* const* models, int dtype, cons
   return batch(n, models, true, dtype, s, x, stream);
 }
 
+int aroam_solve_footprint(const aroam_model* model, int kind, const aroam_solve_opts* opts,
+                          size_t* bytes) {
+  aroam::clear_error();
+  if (!model || !opts || !bytes || (kind != 0 && kind != 1)) {
+    aroam::set_error("bad arguments to aroam_solve_footprint");
+    return AROAM_EINVAL;
+  }
+  *bytes = aroam::solver_footprint(*model->m, kind, *opts);
+  return AROAM_OK;
+}
+
+struct aroam_server {
+  aroam::Server* s;
+};
+
+int aroam_server_create(size_t hbm_budget_bytes, int max_slots, int tick_iters,
+                        aroam_server** out) {
+  aroam::clear_error();
+  if (!out) {
+    aroam::set_error("NULL output handle");
+    return AROAM_EINVAL;
+  }
+  *out = nullptr;
+  aroam::Server* s = nullptr;
+  const int rc = aroam::server_create(hbm_budget_bytes, max_slots, tick_iters, &s);
+  if (rc != AROAM_OK) return rc;
+  *out = new (std::nothrow) aroam_server{s};
+  if (!*out) {
+    aroam::server_destroy(s);
+    aroam::set_error("host allocation failed");
+    return AROAM_ENOMEM;
+  }
+  return AROAM_OK;
+}
+
+int aroam_server_submit(aroam_server* server, const aroam_model* model, int kind,
+                        const aroam_solve_opts* opts, const void* s, void* x, long long* id) {
+  aroam::clear_error();
+  if (!server || !model || !opts) {
+    aroam::set_error("NULL argument to aroam_server_submit");
+    return AROAM_EINVAL;
+  }
+  return aroam::server_submit(*server->s, *model->m, kind, *opts, s, x, id);
+}
+
+int aroam_server_poll(aroam_server* server, int* n_resident, int* n_queued) {
+  aroam::clear_error();
+  if (!server) {
+    aroam::set_error("NULL server");
+    return AROAM_EINVAL;
+  }
+  return aroam::server_poll(*server->s, n_resident, n_queued);
+}
+
+int aroam_server_collect(aroam_server* server, int max, long long* ids, aroam_solve_info* infos,
+                         int* n) {
+  aroam::clear_error();
+  if (!server) {
+    aroam::set_error("NULL server");
+    return AROAM_EINVAL;
+  }
+  return aroam::server_collect(*server->s, max, ids, infos, n);
+}
+
+void aroam_server_destroy(aroam_server* server) {
+  if (!server) return;
+  aroam::server_destroy(server->s);
+  delete server;
+}
+
 void aroam_model_destroy(aroam_model* model) {
   if (!model) return;
   aroam::destroy_model(model->m);

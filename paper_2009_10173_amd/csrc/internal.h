@@ -142,10 +142,32 @@ int apply_batch(int n, const Model* const* ms, bool adjoint, int dtype, const fl
                 float* const* out, hipStream_t st);
 
 // solvers.hip
+// A solver whose work is enqueued step by step on its stream (kind 0 = LSQR, 1 = FISTA).
+class Solver {
+ public:
+  virtual ~Solver() {}
+  virtual int step(int n_iters) = 0;              // enqueue up to n more iterations
+  virtual bool all_enqueued() const = 0;
+  virtual long long total_iters() const = 0;      // iterations incl. power method / sweeps
+  virtual int finish(aroam_solve_info* info) = 0; // synchronise the stream and report
+  hipStream_t stream = nullptr;
+};
+int solver_create(const Model& m, int kind, const aroam_solve_opts& o, const void* s, void* x,
+                  hipStream_t st, Solver** out);
+size_t solver_footprint(const Model& m, int kind, const aroam_solve_opts& o);
 int solve_lsqr(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
                aroam_solve_info* info, hipStream_t st);
 int solve_l1(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
              aroam_solve_info* info, hipStream_t st);
+
+// serve.hip
+struct Server;
+int server_create(size_t budget, int max_slots, int tick, Server** out);
+int server_submit(Server& sv, const Model& m, int kind, const aroam_solve_opts& o, const void* s,
+                  void* x, long long* id);
+int server_poll(Server& sv, int* n_resident, int* n_queued);
+int server_collect(Server& sv, int max, long long* ids, aroam_solve_info* infos, int* n);
+void server_destroy(Server* sv);
 
 inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 inline long long round_up(long long a, long long b) { return ceil_div(a, b) * b; }

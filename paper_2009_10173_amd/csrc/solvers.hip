@@ -105,17 +105,20 @@ struct LsqrDev {
   double lambda;
   double nrm_u2, nrm_v2, red;
   int done, bad, bad_iter, iter;
+  int failed;  // sticky across the solves of a refinement schedule: an earlier solve failed
 };
 
-__device__ inline bool stop(const LsqrDev* d) { return d->done || d->bad; }
+__device__ inline bool stop(const LsqrDev* d) { return d->done || d->bad || d->failed; }
 
-__global__ void k_lsqr_reset(LsqrDev* d, double damp, double gamma) {
+// Start a new LSQR solve in the state block; `first` clears the sticky failure flag.
+__global__ void k_lsqr_reset(LsqrDev* d, double damp, double gamma, int first) {
   LsqrDev h = {};
   h.damp = damp;
   h.gamma = gamma;
   h.lambda = damp * damp;
   h.su = 1.0;
   h.sv = 1.0;
+  h.failed = first ? 0 : (d->failed || d->bad);
   *d = h;
 }
 
@@ -343,104 +346,11 @@ __global__ __launch_bounds__(256) void k_fista_step(T* __restrict__ y, T* __rest
 
 // ------------------------------------------------------------------------------------------
 
+// Solver objects: creation enqueues the set-up, step(n) enqueues the next n iterations, and
+// finish() synchronises once.  The blocking entry points run create + step(all) + finish;
+// the request scheduler interleaves the steps of many solvers on separate streams.
+
 int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>(ceil_div(n, 256), 4096)); }
-
-template <typename T>
-struct Work {
-  std::vector<void*> ptrs;
-  hipStream_t st;
-  int alloc(T** p, long long n) {
-    void* q = nullptr;
-    AROAM_HIP(hipMallocAsync(&q, (size_t)std::max<long long>(1, n) * sizeof(T), st));
-    ptrs.push_back(q);
-    *p = (T*)q;
-    return AROAM_OK;
-  }
-  int alloc_bytes(void** p, size_t b) {
-    AROAM_HIP(hipMallocAsync(p, std::max<size_t>(1, b), st));
-    ptrs.push_back(*p);
-    return AROAM_OK;
-  }
-  ~Work() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, st);
-  }
-};
-
-template <typename T>
-struct Ctx {
-  const Model& m;
-  hipStream_t st;
-  long long ns, nx;  // signal and image lengths
-  void* stage_f;     // stage buffers for forward / adjoint (large enough for any dtype used)
-  void* stage_a;
-  double* part0;
-  double* part1;
-};
-
-template <typename T>
-int reduce_sq(Ctx<T>& c, const T* a, long long n, double* out) {
-  hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, c.st, a,
-                     (const T*)nullptr, n, c.part0);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, c.st, c.part0, (const double*)nullptr,
-                     kRedBlocks, false, out);
-  AROAM_HIP(hipGetLastError());
-  return AROAM_OK;
-}
-
-// One LSQR solve: min ||[b1; b2] - [A; gamma I] x||^2 + damp^2 ||x||^2 (b2 / gamma only for
-// the stacked correction system).  x receives the result.
-template <typename T>
-int lsqr_run(Ctx<T>& c, int dtype, int iters, double damp, double gamma, int lambda_rule,
-             const T* b1, const T* b2, T* x, LsqrDev* d, Work<T>& w) {
-  T *u, *v, *wv, *ts, *tx, *u2 = nullptr;
-  AROAM_TRY(w.alloc(&u, c.ns));
-  AROAM_TRY(w.alloc(&ts, c.ns));
-  AROAM_TRY(w.alloc(&v, c.nx));
-  AROAM_TRY(w.alloc(&wv, c.nx));
-  AROAM_TRY(w.alloc(&tx, c.nx));
-  if (b2) AROAM_TRY(w.alloc(&u2, c.nx));
-  hipLaunchKernelGGL(k_lsqr_reset, dim3(1), dim3(1), 0, c.st, d, damp, b2 ? gamma : 0.0);
-  const int gx = grid_for(c.nx);
-  // u = b, beta = ||b||
-  AROAM_HIP(hipMemcpyAsync(u, b1, c.ns * sizeof(T), hipMemcpyDeviceToDevice, c.st));
-  if (b2) AROAM_HIP(hipMemcpyAsync(u2, b2, c.nx * sizeof(T), hipMemcpyDeviceToDevice, c.st));
-  hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, c.st, (const T*)u,
-                     (const T*)nullptr, c.ns, c.part0);
-  if (b2)
-    hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, c.st,
-                       (const T*)u2, (const T*)nullptr, c.nx, c.part1);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, c.st, c.part0,
-                     b2 ? c.part1 : (const double*)nullptr, kRedBlocks, false, &d->red);
-  hipLaunchKernelGGL(k_lsqr_beta, dim3(1), dim3(1), 0, c.st, d);
-  // v = A^T u / beta, alpha = ||v||
-  AROAM_TRY(apply(c.m, true, dtype, u, tx, c.stage_a, c.st));
-  hipLaunchKernelGGL(k_lsqr_v<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, c.st, (const T*)tx,
-                     (const T*)u2, v, c.nx, 1, d, c.part0);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, c.st, c.part0, (const double*)nullptr,
-                     kRedBlocks, false, &d->red);
-  hipLaunchKernelGGL(k_lsqr_init_alpha, dim3(1), dim3(1), 0, c.st, d, lambda_rule);
-  hipLaunchKernelGGL(k_lsqr_xw<T>, dim3(gx), dim3(256), 0, c.st, x, wv, (const T*)v, c.nx, 1,
-                     (const LsqrDev*)d);
-  AROAM_HIP(hipGetLastError());
-  for (int it = 0; it < iters; ++it) {
-    AROAM_TRY(apply(c.m, false, dtype, v, ts, c.stage_f, c.st));
-    hipLaunchKernelGGL(k_lsqr_u<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, c.st, (const T*)ts, u,
-                       c.ns, (const T*)v, u2, c.nx, (const LsqrDev*)d, c.part0, c.part1);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, c.st, c.part0,
-                       b2 ? c.part1 : (const double*)nullptr, kRedBlocks, false, &d->red);
-    hipLaunchKernelGGL(k_lsqr_beta, dim3(1), dim3(1), 0, c.st, d);
-    AROAM_TRY(apply(c.m, true, dtype, u, tx, c.stage_a, c.st));
-    hipLaunchKernelGGL(k_lsqr_v<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, c.st, (const T*)tx,
-                       (const T*)u2, v, c.nx, 0, (const LsqrDev*)d, c.part0);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, c.st, c.part0,
-                       (const double*)nullptr, kRedBlocks, false, &d->red);
-    hipLaunchKernelGGL(k_lsqr_rotate, dim3(1), dim3(1), 0, c.st, d);
-    hipLaunchKernelGGL(k_lsqr_xw<T>, dim3(gx), dim3(256), 0, c.st, x, wv, (const T*)v, c.nx, 0,
-                       (const LsqrDev*)d);
-    AROAM_HIP(hipGetLastError());
-  }
-  return AROAM_OK;
-}
 
 int check_dtype(const Model& m, int dt) {
   AROAM_CHECK(dt >= AROAM_FP64 && dt <= AROAM_FP8E4M3, AROAM_EINVAL, "bad dtype %d", dt);
@@ -448,225 +358,435 @@ int check_dtype(const Model& m, int dt) {
   return AROAM_OK;
 }
 
+size_t vec_bytes(long long n, size_t esize) { return (size_t)round_up(std::max<long long>(1, n) * esize, 256); }
+
 template <typename T>
-int setup_ctx(Ctx<T>& c, Work<T>& w, int inner, int outer) {
-  size_t sf = std::max(stage_bytes(c.m, false, inner), stage_bytes(c.m, false, outer));
-  size_t sa = std::max(stage_bytes(c.m, true, inner), stage_bytes(c.m, true, outer));
-  AROAM_TRY(w.alloc_bytes(&c.stage_f, sf));
-  AROAM_TRY(w.alloc_bytes(&c.stage_a, sa));
-  AROAM_TRY(w.alloc_bytes((void**)&c.part0, kRedBlocks * sizeof(double)));
-  AROAM_TRY(w.alloc_bytes((void**)&c.part1, kRedBlocks * sizeof(double)));
+class SolverT final : public Solver {
+ public:
+  SolverT(const Model& m, int kind, const aroam_solve_opts& o, const T* s, T* x, hipStream_t st)
+      : m_(m), kind_(kind), o_(o), s_(s), x_(x) {
+    stream = st;
+    ns_ = (long long)m.grid.ny * m.grid.nx * m.grid.nt;
+    nx_ = (long long)m.grid.ny * m.grid.nx * m.grid.nz;
+  }
+  ~SolverT() override {
+    for (void* p : allocs_) (void)hipFreeAsync(p, stream);
+  }
+
+  // Device bytes the solver allocates (stage buffers, reductions, state, vectors).
+  static size_t footprint(const Model& m, int kind, const aroam_solve_opts& o) {
+    const long long ns = (long long)m.grid.ny * m.grid.nx * m.grid.nt;
+    const long long nx = (long long)m.grid.ny * m.grid.nx * m.grid.nz;
+    size_t b = std::max(stage_bytes(m, false, o.inner), stage_bytes(m, false, o.outer)) +
+               std::max(stage_bytes(m, true, o.inner), stage_bytes(m, true, o.outer)) +
+               2 * vec_bytes(kRedBlocks, 8) + 2 * vec_bytes(1, 512);
+    const size_t e = sizeof(T);
+    if (kind == 0) {
+      b += 2 * vec_bytes(ns, e) + 3 * vec_bytes(nx, e);  // u, ts; v, w, tx
+      if (o.refine_sweeps > 0) b += vec_bytes(ns, e) + 4 * vec_bytes(nx, e);  // rs; u2, gx, rx, dx
+    } else {
+      b += vec_bytes(ns, e) + 4 * vec_bytes(nx, e);  // ts; y, xp, tx, v
+      if (o.inner != o.outer) b += 3 * vec_bytes(nx, e);  // ga, xa, dv
+    }
+    return b;
+  }
+
+  int create() {
+    AROAM_TRY(check_dtype(m_, o_.inner));
+    AROAM_TRY(check_dtype(m_, o_.outer));
+    AROAM_CHECK(s_ && x_, AROAM_EINVAL, "NULL vector");
+    AROAM_CHECK(o_.iters >= 0 && o_.refine_sweeps >= 0 && o_.power_iters >= 0, AROAM_EINVAL,
+                "negative iteration count");
+    AROAM_TRY(alloc_bytes(&stage_f_, std::max(stage_bytes(m_, false, o_.inner),
+                                              stage_bytes(m_, false, o_.outer))));
+    AROAM_TRY(alloc_bytes(&stage_a_, std::max(stage_bytes(m_, true, o_.inner),
+                                              stage_bytes(m_, true, o_.outer))));
+    AROAM_TRY(alloc_bytes((void**)&part0_, kRedBlocks * sizeof(double)));
+    AROAM_TRY(alloc_bytes((void**)&part1_, kRedBlocks * sizeof(double)));
+    return kind_ == 0 ? create_lsqr() : create_l1();
+  }
+
+  int step(int n) override { return kind_ == 0 ? step_lsqr(n) : step_l1(n); }
+  bool all_enqueued() const override { return enqueued_ >= total_; }
+  long long total_iters() const override { return total_; }
+  int finish(aroam_solve_info* info) override { return kind_ == 0 ? finish_lsqr(info) : finish_l1(info); }
+
+ private:
+  const Model& m_;
+  int kind_;
+  aroam_solve_opts o_;
+  const T* s_;
+  T* x_;
+  long long ns_ = 0, nx_ = 0;
+  std::vector<void*> allocs_;
+  void *stage_f_ = nullptr, *stage_a_ = nullptr;
+  double *part0_ = nullptr, *part1_ = nullptr;
+  long long total_ = 0, enqueued_ = 0;
+  // LSQR
+  LsqrDev* d_ = nullptr;
+  T *u_ = nullptr, *ts_ = nullptr, *v_ = nullptr, *w_ = nullptr, *tx_ = nullptr, *u2_ = nullptr;
+  T *rs_ = nullptr, *gx_ = nullptr, *rx_ = nullptr, *dx_ = nullptr;
+  int phase_ = 0, it_ = 0;  // LSQR phase: 0 main solve, k = correction solve of sweep k
+  double lam_ = 0, gam_ = 0;
+  // FISTA
+  FistaDev* f_ = nullptr;
+  T *y_ = nullptr, *xp_ = nullptr, *ga_ = nullptr, *xa_ = nullptr, *dv_ = nullptr;
+  int npow_ = 0, period_ = 5, warmup_ = 0;
+  double t_ = 1.0;
+
+  int alloc_bytes(void** p, size_t b) {
+    AROAM_HIP(hipMallocAsync(p, std::max<size_t>(1, b), stream));
+    allocs_.push_back(*p);
+    return AROAM_OK;
+  }
+  int alloc(T** p, long long n) { return alloc_bytes((void**)p, vec_bytes(n, sizeof(T))); }
+  int fwd(int dt, const T* in, T* out) { return apply(m_, false, dt, in, out, stage_f_, stream); }
+  int adj(int dt, const T* in, T* out) { return apply(m_, true, dt, in, out, stage_a_, stream); }
+
+  int reduce_sq(const T* a, long long n, double* out) {
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream, a,
+                       (const T*)nullptr, n, part0_);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, stream, part0_,
+                       (const double*)nullptr, kRedBlocks, false, out);
+    AROAM_HIP(hipGetLastError());
+    return AROAM_OK;
+  }
+
+  // ---- LSQR ------------------------------------------------------------------------------
+  // Start one LSQR solve of min ||[b1; b2] - [A; gamma I] x||^2 + damp^2 ||x||^2 into xout
+  // (b2 / gamma only for a correction solve of the refinement).
+  int lsqr_init(const T* b1, const T* b2, T* xout, double damp, double gamma, int rule, int first) {
+    const int gx = grid_for(nx_);
+    hipLaunchKernelGGL(k_lsqr_reset, dim3(1), dim3(1), 0, stream, d_, damp, b2 ? gamma : 0.0, first);
+    AROAM_HIP(hipMemcpyAsync(u_, b1, ns_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    if (b2) AROAM_HIP(hipMemcpyAsync(u2_, b2, nx_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                       (const T*)u_, (const T*)nullptr, ns_, part0_);
+    if (b2)
+      hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                         (const T*)u2_, (const T*)nullptr, nx_, part1_);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, stream, part0_,
+                       b2 ? part1_ : (const double*)nullptr, kRedBlocks, false, &d_->red);
+    hipLaunchKernelGGL(k_lsqr_beta, dim3(1), dim3(1), 0, stream, d_);
+    AROAM_TRY(adj(o_.inner, u_, tx_));
+    hipLaunchKernelGGL(k_lsqr_v<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                       (const T*)tx_, (const T*)(b2 ? u2_ : nullptr), v_, nx_, 1,
+                       (const LsqrDev*)d_, part0_);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, stream, part0_,
+                       (const double*)nullptr, kRedBlocks, false, &d_->red);
+    hipLaunchKernelGGL(k_lsqr_init_alpha, dim3(1), dim3(1), 0, stream, d_, rule);
+    hipLaunchKernelGGL(k_lsqr_xw<T>, dim3(gx), dim3(256), 0, stream, xout, w_, (const T*)v_,
+                       nx_, 1, (const LsqrDev*)d_);
+    AROAM_HIP(hipGetLastError());
+    return AROAM_OK;
+  }
+
+  int lsqr_iter(bool stacked, T* xout) {
+    const int gx = grid_for(nx_);
+    AROAM_TRY(fwd(o_.inner, v_, ts_));
+    hipLaunchKernelGGL(k_lsqr_u<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                       (const T*)ts_, u_, ns_, (const T*)v_, stacked ? u2_ : (T*)nullptr, nx_,
+                       (const LsqrDev*)d_, part0_, part1_);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, stream, part0_,
+                       stacked ? part1_ : (const double*)nullptr, kRedBlocks, false, &d_->red);
+    hipLaunchKernelGGL(k_lsqr_beta, dim3(1), dim3(1), 0, stream, d_);
+    AROAM_TRY(adj(o_.inner, u_, tx_));
+    hipLaunchKernelGGL(k_lsqr_v<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                       (const T*)tx_, (const T*)(stacked ? u2_ : nullptr), v_, nx_, 0,
+                       (const LsqrDev*)d_, part0_);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, stream, part0_,
+                       (const double*)nullptr, kRedBlocks, false, &d_->red);
+    hipLaunchKernelGGL(k_lsqr_rotate, dim3(1), dim3(1), 0, stream, d_);
+    hipLaunchKernelGGL(k_lsqr_xw<T>, dim3(gx), dim3(256), 0, stream, xout, w_, (const T*)v_,
+                       nx_, 0, (const LsqrDev*)d_);
+    AROAM_HIP(hipGetLastError());
+    return AROAM_OK;
+  }
+
+  int create_lsqr() {
+    AROAM_TRY(alloc_bytes((void**)&d_, sizeof(LsqrDev)));
+    AROAM_TRY(alloc(&u_, ns_));
+    AROAM_TRY(alloc(&ts_, ns_));
+    AROAM_TRY(alloc(&v_, nx_));
+    AROAM_TRY(alloc(&w_, nx_));
+    AROAM_TRY(alloc(&tx_, nx_));
+    int rule = o_.lambda < 0;
+    lam_ = rule ? 0.0 : o_.lambda;
+    if (o_.refine_sweeps > 0) {
+      AROAM_TRY(alloc(&u2_, nx_));
+      AROAM_TRY(alloc(&rs_, ns_));
+      AROAM_TRY(alloc(&gx_, nx_));
+      AROAM_TRY(alloc(&rx_, nx_));
+      AROAM_TRY(alloc(&dx_, nx_));
+    }
+    if (rule && (o_.refine_sweeps > 0 || o_.inner != o_.outer)) {
+      // Tikhonov rule 1e-2 ||A^T s||_2 with the high-precision adjoint; the correction
+      // solves also need sqrt(lambda) on the host, so the value is read back once
+      AROAM_TRY(adj(o_.outer, s_, tx_));
+      AROAM_TRY(reduce_sq(tx_, nx_, &d_->red));
+      double red = 0.0;
+      AROAM_HIP(hipMemcpyAsync(&red, &d_->red, sizeof(red), hipMemcpyDeviceToHost, stream));
+      AROAM_HIP(hipStreamSynchronize(stream));
+      lam_ = 1e-2 * std::sqrt(red);
+      rule = 0;
+    }
+    AROAM_TRY(lsqr_init(s_, nullptr, x_, std::sqrt(lam_), 0.0, rule, 1));
+    gam_ = std::sqrt(lam_);
+    AROAM_CHECK(o_.refine_sweeps == 0 || gam_ > 0, AROAM_EINVAL,
+                "refinement sweeps need lambda > 0");
+    total_ = (long long)o_.iters * (1 + o_.refine_sweeps);
+    phase_ = 0;
+    it_ = 0;
+    if (o_.iters == 0) enqueued_ = total_;
+    return AROAM_OK;
+  }
+
+  // End of the current solve: a correction is added to x; then the next sweep starts.
+  int lsqr_next_phase() {
+    if (phase_ > 0) {
+      hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(nx_)), dim3(256), 0, stream, x_, (const T*)x_,
+                         (const T*)dx_, 1.0, 1.0, nx_);
+      AROAM_HIP(hipGetLastError());
+    }
+    if (phase_ >= o_.refine_sweeps) return AROAM_OK;
+    // high-precision residual of the normal equations g = A^T (s - A x) - lambda x; the
+    // correction solves min || [A; sqrt(lambda) I] d - [0; g / sqrt(lambda)] ||
+    AROAM_TRY(fwd(o_.outer, x_, rs_));
+    hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(ns_)), dim3(256), 0, stream, rs_, s_,
+                       (const T*)rs_, 1.0, -1.0, ns_);
+    AROAM_TRY(adj(o_.outer, rs_, gx_));
+    hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(nx_)), dim3(256), 0, stream, rx_, (const T*)gx_,
+                       (const T*)x_, 1.0 / gam_, -gam_, nx_);
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ns_)), dim3(256), 0, stream, rs_, 0.0, ns_);
+    AROAM_HIP(hipGetLastError());
+    ++phase_;
+    it_ = 0;
+    return lsqr_init(rs_, rx_, dx_, 0.0, gam_, 0, 0);
+  }
+
+  int step_lsqr(int n) {
+    while (n > 0 && enqueued_ < total_) {
+      if (it_ == o_.iters) AROAM_TRY(lsqr_next_phase());
+      AROAM_TRY(lsqr_iter(phase_ > 0, phase_ > 0 ? dx_ : x_));
+      ++it_;
+      ++enqueued_;
+      --n;
+      if (enqueued_ == total_ && phase_ > 0) AROAM_TRY(lsqr_next_phase());
+    }
+    return AROAM_OK;
+  }
+
+  int finish_lsqr(aroam_solve_info* info) {
+    LsqrDev h;
+    AROAM_HIP(hipMemcpyAsync(&h, d_, sizeof(h), hipMemcpyDeviceToHost, stream));
+    AROAM_HIP(hipStreamSynchronize(stream));
+    const bool bad = h.bad || h.failed;
+    const int done = (int)std::min<long long>(enqueued_, (long long)phase_ * o_.iters + h.iter);
+    if (info) {
+      info->iters_done = bad ? (int)((long long)phase_ * o_.iters + h.bad_iter) : done;
+      info->status = bad ? AROAM_ENONFINITE : AROAM_OK;
+      info->lambda = phase_ > 0 ? lam_ : h.lambda;
+      info->lipschitz = 0.0;
+      info->rnorm = std::fabs(h.phibar);
+      info->alpha = h.alpha;
+      info->beta = h.beta;
+    }
+    if (bad) {
+      set_error("non-finite value in LSQR");
+      return AROAM_ENONFINITE;
+    }
+    return AROAM_OK;
+  }
+
+  // ---- FISTA -----------------------------------------------------------------------------
+  int create_l1() {
+    npow_ = o_.lipschitz > 0 ? 0 : (o_.power_iters > 0 ? o_.power_iters : 50);
+    period_ = o_.anchor_period > 0 ? o_.anchor_period : 5;
+    warmup_ = o_.anchor_warmup >= 0 ? o_.anchor_warmup : o_.iters / 4;
+    AROAM_TRY(alloc_bytes((void**)&f_, sizeof(FistaDev)));
+    AROAM_TRY(alloc(&y_, nx_));
+    AROAM_TRY(alloc(&xp_, nx_));
+    AROAM_TRY(alloc(&ts_, ns_));
+    AROAM_TRY(alloc(&tx_, nx_));
+    AROAM_TRY(alloc(&v_, nx_));
+    if (o_.inner != o_.outer) {
+      AROAM_TRY(alloc(&ga_, nx_));
+      AROAM_TRY(alloc(&xa_, nx_));
+      AROAM_TRY(alloc(&dv_, nx_));
+    }
+    const int gx = grid_for(nx_);
+    hipLaunchKernelGGL(k_fista_reset, dim3(1), dim3(1), 0, stream, f_);
+    if (npow_ > 0) {
+      if (o_.power_start)
+        AROAM_HIP(hipMemcpyAsync(v_, o_.power_start, nx_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
+      else
+        hipLaunchKernelGGL(k_fill<T>, dim3(gx), dim3(256), 0, stream, v_, 1.0, nx_);
+      AROAM_TRY(reduce_sq(v_, nx_, &f_->ww));
+      hipLaunchKernelGGL(k_power_start, dim3(1), dim3(1), 0, stream, f_);
+      hipLaunchKernelGGL(k_scale_dev<T>, dim3(gx), dim3(256), 0, stream, v_, (const T*)v_,
+                         (const double*)&f_->inv, nx_);
+    }
+    hipLaunchKernelGGL(k_fill<T>, dim3(gx), dim3(256), 0, stream, xp_, 0.0, nx_);
+    hipLaunchKernelGGL(k_fill<T>, dim3(gx), dim3(256), 0, stream, y_, 0.0, nx_);
+    AROAM_HIP(hipGetLastError());
+    total_ = npow_ + (long long)o_.iters;
+    if (npow_ == 0) AROAM_TRY(l1_params());
+    return AROAM_OK;
+  }
+
+  // L and lambda once the power method is done (lambda rule: 5e-3 max |A^T s|).
+  int l1_params() {
+    const int rule = o_.lambda < 0;
+    if (rule) {
+      AROAM_TRY(adj(o_.outer, s_, tx_));
+      hipLaunchKernelGGL(k_amax_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                         (const T*)tx_, nx_, part0_);
+      hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, stream, part0_,
+                         (const double*)nullptr, kRedBlocks, true, &f_->amax);
+    }
+    hipLaunchKernelGGL(k_fista_params, dim3(1), dim3(1), 0, stream, f_, o_.lipschitz, o_.lambda, rule);
+    AROAM_HIP(hipGetLastError());
+    return AROAM_OK;
+  }
+
+  int power_iter() {
+    const int gx = grid_for(nx_);
+    AROAM_TRY(fwd(o_.outer, v_, ts_));
+    AROAM_TRY(adj(o_.outer, ts_, tx_));
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                       (const T*)v_, (const T*)tx_, nx_, part0_);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, stream, part0_,
+                       (const double*)nullptr, kRedBlocks, false, &f_->vv);
+    AROAM_TRY(reduce_sq(tx_, nx_, &f_->ww));
+    hipLaunchKernelGGL(k_power_scalars, dim3(1), dim3(1), 0, stream, f_);
+    hipLaunchKernelGGL(k_scale_dev<T>, dim3(gx), dim3(256), 0, stream, v_, (const T*)tx_,
+                       (const double*)&f_->inv, nx_);
+    AROAM_HIP(hipGetLastError());
+    return AROAM_OK;
+  }
+
+  int fista_iter(int it) {
+    const int gx = grid_for(nx_), gs = grid_for(ns_);
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_ * t_));
+    const double mom = (t_ - 1.0) / tn;
+    const bool anchored = o_.inner != o_.outer;
+    if (!anchored) {
+      AROAM_TRY(fwd(o_.inner, y_, ts_));
+      hipLaunchKernelGGL(k_axpby<T>, dim3(gs), dim3(256), 0, stream, ts_, (const T*)ts_, s_, 1.0, -1.0, ns_);
+      AROAM_TRY(adj(o_.inner, ts_, tx_));
+      hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, stream, y_, xp_,
+                         (const T*)nullptr, (const T*)tx_, mom, nx_, (const FistaDev*)f_);
+    } else if (it < warmup_ || (it - warmup_) % period_ == 0) {
+      // anchor: the exact gradient at y in the outer precision
+      AROAM_HIP(hipMemcpyAsync(xa_, y_, nx_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
+      AROAM_TRY(fwd(o_.outer, y_, ts_));
+      hipLaunchKernelGGL(k_axpby<T>, dim3(gs), dim3(256), 0, stream, ts_, (const T*)ts_, s_, 1.0, -1.0, ns_);
+      AROAM_TRY(adj(o_.outer, ts_, tx_));
+      hipLaunchKernelGGL(k_axpby<T>, dim3(gx), dim3(256), 0, stream, ga_, (const T*)tx_,
+                         (const T*)nullptr, 2.0, 0.0, nx_);
+      hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, stream, y_, xp_, (const T*)ga_,
+                         (const T*)nullptr, mom, nx_, (const FistaDev*)f_);
+    } else {
+      // correction: g = g_a + 2 A^T A (y - x_a) with the inner-precision applies
+      hipLaunchKernelGGL(k_axpby<T>, dim3(gx), dim3(256), 0, stream, dv_, (const T*)y_,
+                         (const T*)xa_, 1.0, -1.0, nx_);
+      AROAM_TRY(fwd(o_.inner, dv_, ts_));
+      AROAM_TRY(adj(o_.inner, ts_, tx_));
+      hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, stream, y_, xp_, (const T*)ga_,
+                         (const T*)tx_, mom, nx_, (const FistaDev*)f_);
+    }
+    AROAM_HIP(hipGetLastError());
+    t_ = tn;
+    return AROAM_OK;
+  }
+
+  int step_l1(int n) {
+    while (n > 0 && enqueued_ < total_) {
+      if (enqueued_ < npow_) {
+        AROAM_TRY(power_iter());
+        if (enqueued_ + 1 == npow_) AROAM_TRY(l1_params());
+      } else {
+        AROAM_TRY(fista_iter((int)(enqueued_ - npow_)));
+      }
+      ++enqueued_;
+      --n;
+    }
+    return AROAM_OK;
+  }
+
+  int finish_l1(aroam_solve_info* info) {
+    AROAM_HIP(hipMemcpyAsync(x_, xp_, nx_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    FistaDev h;
+    AROAM_HIP(hipMemcpyAsync(&h, f_, sizeof(h), hipMemcpyDeviceToHost, stream));
+    AROAM_HIP(hipStreamSynchronize(stream));
+    if (info) {
+      info->iters_done = h.bad ? 0 : (int)std::max<long long>(0, enqueued_ - npow_);
+      info->status = h.bad ? AROAM_ENONFINITE : AROAM_OK;
+      info->lambda = h.lambda;
+      info->lipschitz = h.L;
+      info->rnorm = 0.0;
+      info->alpha = h.rq;
+      info->beta = 0.0;
+    }
+    if (h.bad) {
+      set_error("non-finite value in FISTA (Lipschitz constant or lambda)");
+      return AROAM_ENONFINITE;
+    }
+    return AROAM_OK;
+  }
+};
+
+template <typename T>
+int make_solver(const Model& m, int kind, const aroam_solve_opts& o, const void* s, void* x,
+                hipStream_t st, Solver** out) {
+  auto* sv = new (std::nothrow) SolverT<T>(m, kind, o, (const T*)s, (T*)x, st);
+  AROAM_CHECK(sv, AROAM_ENOMEM, "host allocation failed");
+  const int rc = sv->create();
+  if (rc != AROAM_OK) {
+    delete sv;
+    return rc;
+  }
+  *out = sv;
   return AROAM_OK;
 }
 
-template <typename T>
-int lsqr_solve(const Model& m, const aroam_solve_opts& o, const T* s, T* x,
-               aroam_solve_info* info, hipStream_t st) {
-  const int inner = o.inner, outer = o.outer;
-  AROAM_TRY(check_dtype(m, inner));
-  AROAM_TRY(check_dtype(m, outer));
-  AROAM_CHECK(o.iters >= 0 && o.refine_sweeps >= 0, AROAM_EINVAL, "negative iteration count");
-  Work<T> w;
-  w.st = st;
-  Ctx<T> c{m, st, (long long)m.grid.ny * m.grid.nx * m.grid.nt,
-           (long long)m.grid.ny * m.grid.nx * m.grid.nz, nullptr, nullptr, nullptr, nullptr};
-  AROAM_TRY(setup_ctx(c, w, inner, outer));
-  LsqrDev* d = nullptr;
-  AROAM_TRY(w.alloc_bytes((void**)&d, sizeof(LsqrDev)));
-  const int rule = o.lambda < 0;
-  const double damp0 = rule ? 0.0 : std::sqrt(o.lambda);
-  AROAM_TRY(lsqr_run<T>(c, inner, o.iters, damp0, 0.0, rule, s, nullptr, x, d, w));
-  LsqrDev first;
-  AROAM_HIP(hipMemcpyAsync(&first, d, sizeof(first), hipMemcpyDeviceToHost, st));
-  AROAM_HIP(hipStreamSynchronize(st));
-  int status = first.bad ? AROAM_ENONFINITE : AROAM_OK;
-  LsqrDev last = first;
-  int done_total = first.bad ? first.bad_iter : first.iter;
-  if (status == AROAM_OK && o.refine_sweeps > 0) {
-    const double lam = first.lambda;
-    const double g = std::sqrt(lam);
-    AROAM_CHECK(g > 0, AROAM_EINVAL, "refinement sweeps need lambda > 0");
-    T *rs, *gx, *rx, *dx;
-    AROAM_TRY(w.alloc(&rs, c.ns));
-    AROAM_TRY(w.alloc(&gx, c.nx));
-    AROAM_TRY(w.alloc(&rx, c.nx));
-    AROAM_TRY(w.alloc(&dx, c.nx));
-    for (int sw = 0; sw < o.refine_sweeps; ++sw) {
-      // high-precision residual of the normal equations: g = A^T (s - A x) - lam x.  The
-      // correction solves min || [A; sqrt(lam) I] d - [0; g / sqrt(lam)] || at low precision.
-      AROAM_TRY(apply(m, false, outer, x, rs, c.stage_f, st));
-      hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(c.ns)), dim3(256), 0, st, rs, s, (const T*)rs,
-                         1.0, -1.0, c.ns);
-      AROAM_TRY(apply(m, true, outer, rs, gx, c.stage_a, st));
-      hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(c.nx)), dim3(256), 0, st, rx, (const T*)gx,
-                         (const T*)x, 1.0 / g, -g, c.nx);
-      hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(c.ns)), dim3(256), 0, st, rs, 0.0, c.ns);
-      AROAM_HIP(hipGetLastError());
-      AROAM_TRY(lsqr_run<T>(c, inner, o.iters, 0.0, g, 0, rs, rx, dx, d, w));
-      hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(c.nx)), dim3(256), 0, st, x, (const T*)x,
-                         (const T*)dx, 1.0, 1.0, c.nx);
-      AROAM_HIP(hipGetLastError());
-      AROAM_HIP(hipMemcpyAsync(&last, d, sizeof(last), hipMemcpyDeviceToHost, st));
-      AROAM_HIP(hipStreamSynchronize(st));
-      if (last.bad) {
-        status = AROAM_ENONFINITE;
-        done_total += last.bad_iter;
-        break;
-      }
-      done_total += last.iter;
-    }
-  }
-  AROAM_HIP(hipStreamSynchronize(st));
-  if (info) {
-    info->iters_done = done_total;
-    info->status = status;
-    info->lambda = first.lambda;
-    info->lipschitz = 0.0;
-    info->rnorm = std::fabs(last.phibar);
-    info->alpha = last.alpha;
-    info->beta = last.beta;
-  }
-  if (status != AROAM_OK) set_error("non-finite value in LSQR after %d iterations", done_total);
-  return status;
-}
-
-template <typename T>
-int l1_solve(const Model& m, const aroam_solve_opts& o, const T* s, T* x, aroam_solve_info* info,
-             hipStream_t st) {
-  const int inner = o.inner, outer = o.outer;
-  AROAM_TRY(check_dtype(m, inner));
-  AROAM_TRY(check_dtype(m, outer));
-  AROAM_CHECK(o.iters >= 0, AROAM_EINVAL, "negative iteration count");
-  const int npow = o.power_iters > 0 ? o.power_iters : 50;
-  const int period = o.anchor_period > 0 ? o.anchor_period : 5;
-  const int warmup = o.anchor_warmup >= 0 ? o.anchor_warmup : o.iters / 4;
-  const bool anchored = inner != outer;
-  Work<T> w;
-  w.st = st;
-  Ctx<T> c{m, st, (long long)m.grid.ny * m.grid.nx * m.grid.nt,
-           (long long)m.grid.ny * m.grid.nx * m.grid.nz, nullptr, nullptr, nullptr, nullptr};
-  AROAM_TRY(setup_ctx(c, w, inner, outer));
-  FistaDev* f = nullptr;
-  AROAM_TRY(w.alloc_bytes((void**)&f, sizeof(FistaDev)));
-  hipLaunchKernelGGL(k_fista_reset, dim3(1), dim3(1), 0, st, f);
-  T *y, *xp, *ts, *tx, *v, *ga = nullptr, *xa = nullptr, *dv = nullptr;
-  AROAM_TRY(w.alloc(&y, c.nx));
-  AROAM_TRY(w.alloc(&xp, c.nx));
-  AROAM_TRY(w.alloc(&ts, c.ns));
-  AROAM_TRY(w.alloc(&tx, c.nx));
-  AROAM_TRY(w.alloc(&v, c.nx));
-  const int gx = grid_for(c.nx), gs = grid_for(c.ns);
-  // Lipschitz constant: power method on A^T A in the outer precision
-  if (o.lipschitz <= 0) {
-    if (o.power_start)
-      AROAM_HIP(hipMemcpyAsync(v, o.power_start, c.nx * sizeof(T), hipMemcpyDeviceToDevice, st));
-    else
-      hipLaunchKernelGGL(k_fill<T>, dim3(gx), dim3(256), 0, st, v, 1.0, c.nx);
-    AROAM_TRY(reduce_sq<T>(c, v, c.nx, &f->ww));
-    hipLaunchKernelGGL(k_power_start, dim3(1), dim3(1), 0, st, f);
-    hipLaunchKernelGGL(k_scale_dev<T>, dim3(gx), dim3(256), 0, st, v, (const T*)v,
-                       (const double*)&f->inv, c.nx);
-    for (int it = 0; it < npow; ++it) {
-      AROAM_TRY(apply(m, false, outer, v, ts, c.stage_f, st));
-      AROAM_TRY(apply(m, true, outer, ts, tx, c.stage_a, st));
-      hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, (const T*)v,
-                         (const T*)tx, c.nx, c.part0);
-      hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, c.part0,
-                         (const double*)nullptr, kRedBlocks, false, &f->vv);
-      AROAM_TRY(reduce_sq<T>(c, tx, c.nx, &f->ww));
-      hipLaunchKernelGGL(k_power_scalars, dim3(1), dim3(1), 0, st, f);
-      hipLaunchKernelGGL(k_scale_dev<T>, dim3(gx), dim3(256), 0, st, v, (const T*)tx,
-                         (const double*)&f->inv, c.nx);
-      AROAM_HIP(hipGetLastError());
-    }
-  }
-  // lambda rule needs max |A^T s|
-  const int rule = o.lambda < 0;
-  if (rule) {
-    AROAM_TRY(apply(m, true, outer, s, tx, c.stage_a, st));
-    hipLaunchKernelGGL(k_amax_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, (const T*)tx,
-                       c.nx, c.part0);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, c.part0, (const double*)nullptr,
-                       kRedBlocks, true, &f->amax);
-  }
-  hipLaunchKernelGGL(k_fista_params, dim3(1), dim3(1), 0, st, f, o.lipschitz, o.lambda, rule);
-  AROAM_HIP(hipGetLastError());
-  // FISTA from x0 = 0
-  hipLaunchKernelGGL(k_fill<T>, dim3(gx), dim3(256), 0, st, xp, 0.0, c.nx);
-  hipLaunchKernelGGL(k_fill<T>, dim3(gx), dim3(256), 0, st, y, 0.0, c.nx);
-  if (anchored) {
-    AROAM_TRY(w.alloc(&ga, c.nx));
-    AROAM_TRY(w.alloc(&xa, c.nx));
-    AROAM_TRY(w.alloc(&dv, c.nx));
-  }
-  double t = 1.0;
-  for (int it = 0; it < o.iters; ++it) {
-    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-    const double mom = (t - 1.0) / tn;
-    if (!anchored) {
-      AROAM_TRY(apply(m, false, inner, y, ts, c.stage_f, st));
-      hipLaunchKernelGGL(k_axpby<T>, dim3(gs), dim3(256), 0, st, ts, (const T*)ts, s, 1.0, -1.0, c.ns);
-      AROAM_TRY(apply(m, true, inner, ts, tx, c.stage_a, st));
-      hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, st, y, xp, (const T*)nullptr,
-                         (const T*)tx, mom, c.nx, (const FistaDev*)f);
-    } else if (it < warmup || (it - warmup) % period == 0) {
-      // anchor: exact gradient at y in the outer precision
-      AROAM_HIP(hipMemcpyAsync(xa, y, c.nx * sizeof(T), hipMemcpyDeviceToDevice, st));
-      AROAM_TRY(apply(m, false, outer, y, ts, c.stage_f, st));
-      hipLaunchKernelGGL(k_axpby<T>, dim3(gs), dim3(256), 0, st, ts, (const T*)ts, s, 1.0, -1.0, c.ns);
-      AROAM_TRY(apply(m, true, outer, ts, tx, c.stage_a, st));
-      hipLaunchKernelGGL(k_axpby<T>, dim3(gx), dim3(256), 0, st, ga, (const T*)tx,
-                         (const T*)nullptr, 2.0, 0.0, c.nx);
-      hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, st, y, xp, (const T*)ga,
-                         (const T*)nullptr, mom, c.nx, (const FistaDev*)f);
-    } else {
-      // correction: g = g_a + 2 A^T A (y - x_a) with the inner-precision applies
-      hipLaunchKernelGGL(k_axpby<T>, dim3(gx), dim3(256), 0, st, dv, (const T*)y, (const T*)xa,
-                         1.0, -1.0, c.nx);
-      AROAM_TRY(apply(m, false, inner, dv, ts, c.stage_f, st));
-      AROAM_TRY(apply(m, true, inner, ts, tx, c.stage_a, st));
-      hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, st, y, xp, (const T*)ga,
-                         (const T*)tx, mom, c.nx, (const FistaDev*)f);
-    }
-    AROAM_HIP(hipGetLastError());
-    t = tn;
-  }
-  AROAM_HIP(hipMemcpyAsync(x, xp, c.nx * sizeof(T), hipMemcpyDeviceToDevice, st));
-  FistaDev fh;
-  AROAM_HIP(hipMemcpyAsync(&fh, f, sizeof(fh), hipMemcpyDeviceToHost, st));
-  AROAM_HIP(hipStreamSynchronize(st));
-  const int status = fh.bad ? AROAM_ENONFINITE : AROAM_OK;
-  if (info) {
-    info->iters_done = fh.bad ? 0 : o.iters;
-    info->status = status;
-    info->lambda = fh.lambda;
-    info->lipschitz = fh.L;
-    info->rnorm = 0.0;
-    info->alpha = fh.rq;
-    info->beta = 0.0;
-  }
-  if (status != AROAM_OK) set_error("non-finite value in FISTA (Lipschitz constant or lambda)");
-  return status;
+int run_blocking(const Model& m, int kind, const aroam_solve_opts& o, const void* s, void* x,
+                 aroam_solve_info* info, hipStream_t st) {
+  Solver* sv = nullptr;
+  AROAM_TRY(solver_create(m, kind, o, s, x, st, &sv));
+  int rc = sv->step(0x7fffffff);
+  if (rc == AROAM_OK) rc = sv->finish(info);
+  else (void)hipStreamSynchronize(st);
+  delete sv;
+  return rc;
 }
 
 }  // namespace
 
-int solve_lsqr(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
-               aroam_solve_info* info, hipStream_t st) {
+int solver_create(const Model& m, int kind, const aroam_solve_opts& o, const void* s, void* x,
+                  hipStream_t st, Solver** out) {
+  AROAM_CHECK(out && (kind == 0 || kind == 1), AROAM_EINVAL, "bad solver kind");
   AROAM_CHECK(s && x, AROAM_EINVAL, "NULL vector");
   AROAM_CHECK((o.inner == AROAM_FP64) == (o.outer == AROAM_FP64), AROAM_EINVAL,
               "FP64 cannot be mixed with single-precision vectors");
-  if (o.inner == AROAM_FP64) return lsqr_solve<double>(m, o, (const double*)s, (double*)x, info, st);
-  return lsqr_solve<float>(m, o, (const float*)s, (float*)x, info, st);
+  *out = nullptr;
+  if (o.inner == AROAM_FP64) return make_solver<double>(m, kind, o, s, x, st, out);
+  return make_solver<float>(m, kind, o, s, x, st, out);
+}
+
+size_t solver_footprint(const Model& m, int kind, const aroam_solve_opts& o) {
+  if (o.inner == AROAM_FP64) return SolverT<double>::footprint(m, kind, o);
+  return SolverT<float>::footprint(m, kind, o);
+}
+
+int solve_lsqr(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
+               aroam_solve_info* info, hipStream_t st) {
+  return run_blocking(m, 0, o, s, x, info, st);
 }
 
 int solve_l1(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
              aroam_solve_info* info, hipStream_t st) {
-  AROAM_CHECK(s && x, AROAM_EINVAL, "NULL vector");
-  AROAM_CHECK((o.inner == AROAM_FP64) == (o.outer == AROAM_FP64), AROAM_EINVAL,
-              "FP64 cannot be mixed with single-precision vectors");
-  if (o.inner == AROAM_FP64) return l1_solve<double>(m, o, (const double*)s, (double*)x, info, st);
-  return l1_solve<float>(m, o, (const float*)s, (float*)x, info, st);
+  return run_blocking(m, 1, o, s, x, info, st);
 }
 
 }  // namespace aroam

@@ -101,23 +101,34 @@ def _box(g):
 
 def _stamp_points(vol, g, pts, radius, amp):
     """Mark voxels whose centre lies within `radius` of any of the points `pts` [P,3]."""
-    xs, ys, zs = _voxel_axes(g)
+    pts = np.asarray(pts, dtype=np.float64)
+    if pts.size == 0:
+        return
     st, dz = g["step_m"], g["dz_m"]
-    for p in pts:
-        ix0 = max(0, int(math.floor((p[0] - radius) / st)))
-        ix1 = min(g["nx"] - 1, int(math.ceil((p[0] + radius) / st)))
-        iy0 = max(0, int(math.floor((p[1] - radius) / st)))
-        iy1 = min(g["ny"] - 1, int(math.ceil((p[1] + radius) / st)))
-        kz0 = max(0, int(math.floor((p[2] - radius) / dz)) + g["nz"] // 2)
-        kz1 = min(g["nz"] - 1, int(math.ceil((p[2] + radius) / dz)) + g["nz"] // 2)
-        if ix0 > ix1 or iy0 > iy1 or kz0 > kz1:
+    nz2 = g["nz"] // 2
+    rx = int(math.ceil(radius / st)) + 1
+    rz = int(math.ceil(radius / dz)) + 1
+    # candidate voxels: a box around the voxel nearest to each point
+    cx = np.rint(pts[:, 0] / st).astype(np.int64)
+    cy = np.rint(pts[:, 1] / st).astype(np.int64)
+    cz = np.rint(pts[:, 2] / dz).astype(np.int64) + nz2
+    ox, oy, oz = np.meshgrid(np.arange(-rx, rx + 1), np.arange(-rx, rx + 1),
+                             np.arange(-rz, rz + 1), indexing="ij")
+    ox, oy, oz = ox.ravel(), oy.ravel(), oz.ravel()
+    for lo in range(0, len(pts), 4096):
+        sl = slice(lo, lo + 4096)
+        ix = cx[sl, None] + ox[None, :]
+        iy = cy[sl, None] + oy[None, :]
+        iz = cz[sl, None] + oz[None, :]
+        d2 = ((ix * st - pts[sl, 0:1]) ** 2 + (iy * st - pts[sl, 1:2]) ** 2
+              + ((iz - nz2) * dz - pts[sl, 2:3]) ** 2)
+        ok = ((d2 <= radius * radius) & (ix >= 0) & (ix < g["nx"]) & (iy >= 0)
+              & (iy < g["ny"]) & (iz >= 0) & (iz < g["nz"]))
+        if not ok.any():
             continue
-        X = xs[ix0:ix1 + 1][None, :, None]
-        Y = ys[iy0:iy1 + 1][:, None, None]
-        Z = zs[kz0:kz1 + 1][None, None, :]
-        d2 = (X - p[0]) ** 2 + (Y - p[1]) ** 2 + (Z - p[2]) ** 2
-        sub = vol[iy0:iy1 + 1, ix0:ix1 + 1, kz0:kz1 + 1]
-        np.maximum(sub, np.where(d2 <= radius * radius, amp, 0.0), out=sub)
+        flat = np.unique((iy[ok] * g["nx"] + ix[ok]) * g["nz"] + iz[ok])
+        v = vol.reshape(-1)
+        v[flat] = np.maximum(v[flat], amp)
 
 
 def _segment_points(a, b, spacing):
