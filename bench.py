@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests in the serving leg (0 skips it)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -187,10 +189,40 @@ def main():
                      "frac": achieved / peak, "issued_frac": mfma_issued / peak,
                      "traffic": None},
     }
+    # reduced precision with refinement on the same workload: BF16 applies, FP32 residuals
+    log("BF16-refined reconstruction (2 sweeps)")
+    model.solve_lsqr(s, lam=-1.0, iters=iters, inner="bf16", outer="fp32", refine_sweeps=2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    xr, rinfo = model.solve_lsqr(s, lam=-1.0, iters=iters, inner="bf16", outer="fp32",
+                                 refine_sweeps=2)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t1
+    diff = ((xr - x).norm() / x.norm()).item()
+    kt_bf16 = kernel_times(model, "bf16", x0, s, args.kernel_reps)
+    result["bf16_refined"] = {
+        "recon_ms": t_ref * 1e3, "sweeps": 2,
+        "pairs_per_s": ((iters + 0.5) * 3 + 2 + 0.5) / t_ref,
+        "rel_diff_vs_fp32_recon": diff,
+        "kernel_ms": kt_bf16,
+        "issued_frac_bf16": {k: 2.0 * (info["mac_exec"][2] if k == "forward" else
+                                       info["mac_exec_adj"][2]) / (v * 1e-3) / 1e12 / 2500.0
+                             for k, v in kt_bf16.items()},
+    }
+    if args.serve_requests > 0:
+        log(f"serving leg: {args.serve_requests} mixed requests")
+        model.close()
+        model = None
+        from paper_2009_10173_amd import serve as S
+        res = S.main(["--requests", str(args.serve_requests), "--sides", "64,96,128,192",
+                      "--nz", "64,128"], quiet=True)
+        result["serving"] = {k: res[k] for k in ("rate_per_s", "fifo_fp32", "served_fp32",
+                                                  "served_bf16r")}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(cfg, info["mac_alg"])
-    model.close()
+    if model is not None:
+        model.close()
     print(json.dumps(result), flush=True)
 
 

@@ -26,6 +26,10 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
+// Register operands are clang vector types and are reinterpreted with __builtin_bit_cast, so
+// no local variable has its address taken (which would place it in scratch memory).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 
 template <typename Tin, typename Tout>
@@ -104,24 +108,24 @@ struct StagedArgs {
 // the K-group's scale.
 template <typename T, bool FP8A>
 struct AFrag {
-  uint4 v;
+  u32x4 v;
   float sc;
   int mo;
 };
 
 template <typename T, bool FP8A>
-__device__ inline void load_a(const void* __restrict__ pack_raw, const float* __restrict__ gscale,
+__device__ __forceinline__ void load_a(const void* __restrict__ pack_raw, const float* __restrict__ gscale,
                               const int* __restrict__ meta, int b, int g, int n,
                               AFrag<T, FP8A>& f) {
   const int q = b * kLaneGroups + g;
   if constexpr (FP8A) {
-    const uint2 r8 = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(pack_raw) +
+    const u32x2 r8 = *reinterpret_cast<const u32x2*>(reinterpret_cast<const uint8_t*>(pack_raw) +
                                                      ((long long)q * 16 + n) * 8);
-    f.v = make_uint4(r8.x, r8.y, 0u, 0u);
+    f.v = u32x4{r8.x, r8.y, 0u, 0u};
     f.sc = gscale[q];
   } else {
     constexpr int VEC = 16 / sizeof(T);
-    f.v = *reinterpret_cast<const uint4*>(reinterpret_cast<const T*>(pack_raw) +
+    f.v = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(pack_raw) +
                                           ((long long)q * 16 + n) * VEC);
     f.sc = 1.0f;
   }
@@ -129,7 +133,7 @@ __device__ inline void load_a(const void* __restrict__ pack_raw, const float* __
 }
 
 // e4m3 entries of a fragment -> BF16 operand with the K-group's scale applied.
-__device__ inline uint4 decode_fp8(const uint4& v, float sc) {
+__device__ __forceinline__ u32x4 decode_fp8(u32x4 v, float sc) {
   bf16x8 av;
   const floatx2 f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, false);
   const floatx2 f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, true);
@@ -143,7 +147,48 @@ __device__ inline uint4 decode_fp8(const uint4& v, float sc) {
   av[5] = (__bf16)(f2.y * sc);
   av[6] = (__bf16)(f3.x * sc);
   av[7] = (__bf16)(f3.y * sc);
-  return *reinterpret_cast<const uint4*>(&av);
+  return __builtin_bit_cast(u32x4, av);
+}
+
+// Global source and LDS destination of flat stage vector idx of a unit that loads padded
+// patch rows from `lo`, for the chunk starting at inner entry e0.
+struct StageAddr {
+  long long src;
+  int lds;
+};
+
+template <int BR>
+__device__ __forceinline__ StageAddr stage_addr(const StagedArgs& a, int lo, int e0, int idx,
+                                                int py0, int px0, int rowvec, int nvec, int vec) {
+  const int G = lo + idx / rowvec;
+  const int rem = idx % rowvec;
+  const int c = rem / nvec, v = rem % nvec;
+  StageAddr r;
+  r.lds = ((G % BR) * a.NCOL + c) * a.CS + v * vec;
+  r.src = ((long long)(py0 + G) * a.nxp + (px0 + c)) * a.Lp + e0 + v * vec;
+  return r;
+}
+
+// Fetch up to 256 * PF stage vectors of unit u into registers (the rest is loaded when the
+// unit starts); pf_off = -1 marks an unused slot.
+template <typename T, int BR, int PF>
+__device__ __forceinline__ void stage_prefetch(const StagedArgs& a, const T* __restrict__ in,
+                                               int u, int py0, int px0, int rowvec, int nvec,
+                                               u32x4 (&pf)[PF], int (&pf_off)[PF]) {
+  constexpr int VEC = 16 / sizeof(T);
+  const int4 U = a.units[u];
+  const int2 Rr = a.urows[u];
+  const int nv = (Rr.y - Rr.x) * rowvec;
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    const int idx = threadIdx.x + 256 * i;
+    pf_off[i] = -1;
+    if (idx < nv) {
+      const StageAddr sa = stage_addr<BR>(a, Rr.x, U.y, idx, py0, px0, rowvec, nvec, VEC);
+      pf_off[i] = sa.lds;
+      pf[i] = *reinterpret_cast<const u32x4*>(in + sa.src);
+    }
+  }
 }
 
 // LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 rows) and one patch
@@ -166,7 +211,7 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
   constexpr int TPR = BC / 16;
   constexpr int RW = BR / 4;
   constexpr int NT = RW * TPR;
-  constexpr int PF = 2;                // prefetched stage vectors per thread
+  constexpr int PF = 4;                // prefetched stage vectors per thread (>= one row)
   constexpr int PD = 4;                // table-fragment ring depth
   constexpr int CH = 4 * VEC;          // chunk = one bundle's four K-groups... per lane group
   const int tile = blockIdx.y;
@@ -180,31 +225,9 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
   for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int u0 = a.tile_units[tile], u1 = a.tile_units[tile + 1];
   if (u0 < u1) {
-    // stage-vector address of flat index idx of unit (rows [lo, hi)), chunk start e0
-    auto src_of = [&](int lo, int e0, int idx, int& lds_off) -> long long {
-      const int G = lo + idx / rowvec;
-      const int rem = idx % rowvec;
-      const int c = rem / nvec, v = rem % nvec;
-      lds_off = ((G % BR) * a.NCOL + c) * a.CS + v * VEC;
-      return ((long long)(py0 + G) * a.nxp + (px0 + c)) * a.Lp + e0 + v * VEC;
-    };
-    uint4 pf[PF];
+    u32x4 pf[PF];
     int pf_off[PF];
-    auto prefetch = [&](int u) {
-      const int4 U = a.units[u];
-      const int2 Rr = a.urows[u];
-      const int nv = (Rr.y - Rr.x) * rowvec;
-#pragma unroll
-      for (int i = 0; i < PF; ++i) {
-        const int idx = threadIdx.x + 256 * i;
-        pf_off[i] = -1;
-        if (idx < nv) {
-          const long long src = src_of(Rr.x, U.y, idx, pf_off[i]);
-          pf[i] = *reinterpret_cast<const uint4*>(in + src);
-        }
-      }
-    };
-    prefetch(u0);
+    stage_prefetch<T, BR, PF>(a, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
     // table-fragment ring over the tile's whole bundle range
     const int B1 = a.units[u1 - 1].w;
     int bnext = a.units[u0].z;
@@ -220,23 +243,28 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
       __syncthreads();  // every wave is done reading the rows this unit replaces
 #pragma unroll
       for (int i = 0; i < PF; ++i)
-        if (pf_off[i] >= 0) *reinterpret_cast<uint4*>(lds + pf_off[i]) = pf[i];
+        if (pf_off[i] >= 0) *reinterpret_cast<u32x4*>(lds + pf_off[i]) = pf[i];
       const int nv = (Rr.y - Rr.x) * rowvec;
-      for (int base = 256 * PF; base < nv; base += 256 * 8) {  // rows beyond the prefetch
-        uint4 tmp[8];
-        int off[8];
+      // vectors beyond the prefetch (a full ring reload), four loads in flight per thread
+      for (int base = 256 * PF; base < nv; base += 256 * 4) {
+        u32x4 tmp[4];
+        int off[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < 4; ++i) {
           const int idx = base + threadIdx.x + 256 * i;
           off[i] = -1;
-          if (idx < nv) tmp[i] = *reinterpret_cast<const uint4*>(in + src_of(Rr.x, U.y, idx, off[i]));
+          if (idx < nv) {
+            const StageAddr sa = stage_addr<BR>(a, Rr.x, U.y, idx, py0, px0, rowvec, nvec, VEC);
+            off[i] = sa.lds;
+            tmp[i] = *reinterpret_cast<const u32x4*>(in + sa.src);
+          }
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (off[i] >= 0) *reinterpret_cast<uint4*>(lds + off[i]) = tmp[i];
+        for (int i = 0; i < 4; ++i)
+          if (off[i] >= 0) *reinterpret_cast<u32x4*>(lds + off[i]) = tmp[i];
       }
       __syncthreads();
-      if (u + 1 < u1) prefetch(u + 1);
+      if (u + 1 < u1) stage_prefetch<T, BR, PF>(a, in, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
       // LDS base of this lane's positions for the unit's row offset
       const int R = U.x + a.K;
       int lbase[NT];
@@ -251,24 +279,24 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
         for (int j = 0; j + 1 < PD; ++j) ring[j] = ring[j + 1];
         if (bnext < B1) load_a<T, FP8A>(pack_raw, gscale, a.meta, bnext, g, n, ring[PD - 1]);
         ++bnext;
-        uint4 araw;
+        u32x4 araw;
         if constexpr (FP8A) araw = decode_fp8(cur.v, cur.sc);
         else araw = cur.v;
-        uint4 xraw[NT];
+        u32x4 xraw[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) xraw[t] = *reinterpret_cast<const uint4*>(lds + lbase[t] + cur.mo);
+        for (int t = 0; t < NT; ++t) xraw[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + cur.mo);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           if constexpr (sizeof(T) == 4) {
-            const float4 av = *reinterpret_cast<const float4*>(&araw);
-            const float4 xv = *reinterpret_cast<const float4*>(&xraw[t]);
+            const floatx4 av = __builtin_bit_cast(floatx4, araw);
+            const floatx4 xv = __builtin_bit_cast(floatx4, xraw[t]);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[t], 0, 0, 0);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[t], 0, 0, 0);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[t], 0, 0, 0);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[t], 0, 0, 0);
           } else {
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&araw);
-            const bf16x8 xv = *reinterpret_cast<const bf16x8*>(&xraw[t]);
+            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+            const bf16x8 xv = __builtin_bit_cast(bf16x8, xraw[t]);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[t], 0, 0, 0);
           }
         }

@@ -53,7 +53,8 @@ def pairs_of(req, mode):
     kind, o = solver_opts(req, mode)
     if kind == 0:
         sweeps = o["refine_sweeps"]
-        return (o["iters"] + 0.5) * (1 + sweeps) + sweeps
+        rule = 0.5 if (o["lam"] < 0 and (sweeps > 0 or o["inner"] != o["outer"])) else 0.0
+        return (o["iters"] + 0.5) * (1 + sweeps) + sweeps + rule
     return o["power_iters"] + o["iters"] + 0.5
 
 
@@ -171,7 +172,7 @@ def _summary(reqs, rec, mode, wall, extra=None):
     return out
 
 
-def main(argv=None):
+def main(argv=None, quiet=False):
     import torch
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=24)
@@ -214,7 +215,8 @@ def main(argv=None):
     print(f"[serve] served bf16r done", file=sys.stderr, flush=True)
     cache.close()
     torch.cuda.synchronize()
-    print(json.dumps(res), flush=True)
+    if not quiet:
+        print(json.dumps(res), flush=True)
     return res
 
 
