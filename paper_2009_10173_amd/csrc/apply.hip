@@ -106,28 +106,33 @@ struct StagedArgs {
 
 // Table operand of one bundle for one lane: 16 bytes (FP32 / BF16) or 8 bytes of e4m3 plus
 // the K-group's scale.
-template <typename T, bool FP8A>
+// MH 16-row halves of the tile (MH = TM / 16).
+template <typename T, bool FP8A, int MH>
 struct AFrag {
-  u32x4 v;
-  float sc;
+  u32x4 v[MH];
+  float sc[MH];
   int mo;
 };
 
-template <typename T, bool FP8A>
-__device__ __forceinline__ void load_a(const void* __restrict__ pack_raw, const float* __restrict__ gscale,
-                              const int* __restrict__ meta, int b, int g, int n,
-                              AFrag<T, FP8A>& f) {
+template <typename T, bool FP8A, int MH>
+__device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
+                                       const float* __restrict__ gscale,
+                                       const int* __restrict__ meta, int b, int g, int n,
+                                       AFrag<T, FP8A, MH>& f) {
   const int q = b * kLaneGroups + g;
-  if constexpr (FP8A) {
-    const u32x2 r8 = *reinterpret_cast<const u32x2*>(reinterpret_cast<const uint8_t*>(pack_raw) +
-                                                     ((long long)q * 16 + n) * 8);
-    f.v = u32x4{r8.x, r8.y, 0u, 0u};
-    f.sc = gscale[q];
-  } else {
-    constexpr int VEC = 16 / sizeof(T);
-    f.v = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(pack_raw) +
-                                          ((long long)q * 16 + n) * VEC);
-    f.sc = 1.0f;
+#pragma unroll
+  for (int h = 0; h < MH; ++h) {
+    const long long row = (long long)q * (16 * MH) + 16 * h + n;
+    if constexpr (FP8A) {
+      const u32x2 r8 = *reinterpret_cast<const u32x2*>(
+          reinterpret_cast<const uint8_t*>(pack_raw) + row * 8);
+      f.v[h] = u32x4{r8.x, r8.y, 0u, 0u};
+      f.sc[h] = gscale[q * MH + h];
+    } else {
+      constexpr int VEC = 16 / sizeof(T);
+      f.v[h] = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(pack_raw) + row * VEC);
+      f.sc[h] = 1.0f;
+    }
   }
   f.mo = meta[q];
 }
@@ -200,7 +205,7 @@ __device__ __forceinline__ void stage_prefetch(const StagedArgs& a, const T* __r
 // PD-deep register ring that runs across unit boundaries.  Lane (n = lane % 16,
 // g = lane / 16) holds row n of K-group g of the table and the entries of K-group g for
 // position n.
-template <typename T, int BR, int BC, bool FP8A>
+template <typename T, int BR, int BC, bool FP8A, int MH>
 __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ pack_raw,
                                                       const float* __restrict__ gscale,
                                                       const T* __restrict__ in,
@@ -220,9 +225,11 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
   const int n = lane % 16, g = lane / 16;
   constexpr int nvec = CH / VEC;       // 16-byte vectors per staged column
   const int rowvec = a.NCOL * nvec;    // 16-byte vectors per staged row
-  floatx4 acc[NT];
+  floatx4 acc[MH][NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int h = 0; h < MH; ++h)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[h][t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int u0 = a.tile_units[tile], u1 = a.tile_units[tile + 1];
   if (u0 < u1) {
     u32x4 pf[PF];
@@ -231,10 +238,10 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
     // table-fragment ring over the tile's whole bundle range
     const int B1 = a.units[u1 - 1].w;
     int bnext = a.units[u0].z;
-    AFrag<T, FP8A> ring[PD];
+    AFrag<T, FP8A, MH> ring[PD];
 #pragma unroll
     for (int j = 0; j < PD; ++j) {
-      if (bnext < B1) load_a<T, FP8A>(pack_raw, gscale, a.meta, bnext, g, n, ring[j]);
+      if (bnext < B1) load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, bnext, g, n, ring[j]);
       ++bnext;
     }
     for (int u = u0; u < u1; ++u) {
@@ -274,30 +281,33 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
         lbase[t] = (((r + R) % BR) * a.NCOL + c) * a.CS;
       }
       for (int b = U.z; b < U.w; ++b) {
-        const AFrag<T, FP8A> cur = ring[0];
+        const AFrag<T, FP8A, MH> cur = ring[0];
 #pragma unroll
         for (int j = 0; j + 1 < PD; ++j) ring[j] = ring[j + 1];
-        if (bnext < B1) load_a<T, FP8A>(pack_raw, gscale, a.meta, bnext, g, n, ring[PD - 1]);
+        if (bnext < B1) load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, bnext, g, n, ring[PD - 1]);
         ++bnext;
-        u32x4 araw;
-        if constexpr (FP8A) araw = decode_fp8(cur.v, cur.sc);
-        else araw = cur.v;
         u32x4 xraw[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) xraw[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + cur.mo);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          if constexpr (sizeof(T) == 4) {
-            const floatx4 av = __builtin_bit_cast(floatx4, araw);
-            const floatx4 xv = __builtin_bit_cast(floatx4, xraw[t]);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[t], 0, 0, 0);
-          } else {
-            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-            const bf16x8 xv = __builtin_bit_cast(bf16x8, xraw[t]);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[t], 0, 0, 0);
+        for (int h = 0; h < MH; ++h) {
+          u32x4 araw;
+          if constexpr (FP8A) araw = decode_fp8(cur.v[h], cur.sc[h]);
+          else araw = cur.v[h];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            if constexpr (sizeof(T) == 4) {
+              const floatx4 av = __builtin_bit_cast(floatx4, araw);
+              const floatx4 xv = __builtin_bit_cast(floatx4, xraw[t]);
+              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[h][t], 0, 0, 0);
+              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[h][t], 0, 0, 0);
+              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[h][t], 0, 0, 0);
+              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[h][t], 0, 0, 0);
+            } else {
+              const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+              const bf16x8 xv = __builtin_bit_cast(bf16x8, xraw[t]);
+              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[h][t], 0, 0, 0);
+            }
           }
         }
       }
@@ -309,10 +319,12 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
     if (py >= a.ny || px >= a.nx) continue;
     float* o = out + ((long long)py * a.nx + px) * a.out_len;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = kTile * tile + 4 * g + i;
-      if (row < a.out_len) o[row] = acc[t][i];
-    }
+    for (int h = 0; h < MH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * MH * tile + 16 * h + 4 * g + i;
+        if (row < a.out_len) o[row] = acc[h][t][i];
+      }
   }
 }
 
@@ -353,10 +365,11 @@ size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
 
 namespace {
 
-template <typename T, bool FP8A>
+template <typename T, bool FP8A, int MH>
 int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out, hipStream_t st) {
   static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
-  auto kern = k_apply_staged<T, kPatchRows, kPatchCols, FP8A>;
+  AROAM_CHECK(lay.TM == 16 * MH, AROAM_EINVAL, "tile height mismatch");
+  auto kern = k_apply_staged<T, kPatchRows, kPatchCols, FP8A, MH>;
   static bool attr_set = false;  // allow the full LDS of a CU for wide footprints
   if (!attr_set) {
     AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -415,11 +428,11 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
     hipLaunchKernelGGL(k_apply_fma<double>, grid, dim3(256), 0, st, (const double*)pk.d,
                        (const double*)buf, (double*)out, a, lay.G);
   } else if (dtype == AROAM_FP32) {
-    AROAM_TRY((launch_staged<float, false>(lay, pk, buf, out, st)));
+    AROAM_TRY((launch_staged<float, false, 1>(lay, pk, buf, out, st)));
   } else if (dtype == AROAM_BF16) {
-    AROAM_TRY((launch_staged<uint16_t, false>(lay, pk, buf, out, st)));
+    AROAM_TRY((launch_staged<uint16_t, false, kTileRows8 / 16>(lay, pk, buf, out, st)));
   } else {
-    AROAM_TRY((launch_staged<uint16_t, true>(lay, pk, buf, out, st)));
+    AROAM_TRY((launch_staged<uint16_t, true, kTileRows8 / 16>(lay, pk, buf, out, st)));
   }
   AROAM_HIP(hipGetLastError());
   if (!stage) AROAM_HIP(hipFreeAsync(buf, st));

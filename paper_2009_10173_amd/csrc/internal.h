@@ -42,6 +42,7 @@ void clear_error();
 
 constexpr int kTile = 16;     // output rows per tile (time samples or depths) = MFMA M
 constexpr int kLaneGroups = 4; // K-groups per bundle = 64-lane wave / 16
+constexpr int kTileRows8 = 32;  // output rows per tile of the G = 8 (BF16 / FP8) layouts
 constexpr int kPatchRows = 8;   // scan rows per workgroup patch of the staged kernels
 constexpr int kPatchCols = 32;  // scan columns per workgroup patch (two 16-position tiles)
 constexpr int kMaxElements = 4096;  // two FP64 values per sub-element fit in 64 KiB of LDS
@@ -72,6 +73,7 @@ struct PadGeom {
 //    (dx + K) * CS + (run start - chunk start).
 struct Layout {
   int G = 0;
+  int TM = 16;              // output rows per tile (16 or 32: two MFMA row halves)
   int n_tiles = 0;          // output row tiles
   int out_len = 0;          // rows of the output vector (nt or nz)
   long long n_bundles = 0;
@@ -93,8 +95,8 @@ struct Layout {
 };
 
 struct Pack {
-  void* d = nullptr;   // [n_bundles * 4 * 16 * G] elements of the dtype
-  float* d_scale = nullptr;  // FP8 only: per-K-group FP32 scale
+  void* d = nullptr;   // [n_bundles * 4 * TM * G] elements of the dtype
+  float* d_scale = nullptr;  // FP8 only: FP32 scale per (K-group, 16-row half)
   size_t bytes = 0;
 };
 

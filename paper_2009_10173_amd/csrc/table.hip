@@ -155,8 +155,8 @@ __global__ __launch_bounds__(64) void k_table(const int* __restrict__ cdx,
 }
 
 // Fill band tiles: element (group, row m, entry j) of the pack is the table value at
-//   forward: time n = 16 tile + m, depth k = start + j
-//   adjoint: depth k = 16 tile + m, time n = start + j
+//   forward: time n = TM tile + m, depth k = start + j
+//   adjoint: depth k = TM tile + m, time n = start + j
 // of the group's offset, or 0 outside the footprint, the band or the grid.
 template <typename T>
 __device__ inline T cvt(double v);
@@ -188,22 +188,23 @@ __device__ inline double table_value(int oi, int n, int k, int nz, int nt,
 }
 
 template <typename T>
-__global__ void k_pack(long long total, int G, bool adjoint, const int4* __restrict__ groups,
-                       int nz, int nt, const int* __restrict__ colidx,
-                       const int* __restrict__ lo, const long long* __restrict__ off,
-                       const double* __restrict__ band, T* __restrict__ pack) {
+__global__ void k_pack(long long total, int G, int TM, bool adjoint,
+                       const int4* __restrict__ groups, int nz, int nt,
+                       const int* __restrict__ colidx, const int* __restrict__ lo,
+                       const long long* __restrict__ off, const double* __restrict__ band,
+                       T* __restrict__ pack) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const long long grp = idx / (16 * G);
-    const int m = (int)((idx / G) % 16);
+    const long long grp = idx / ((long long)TM * G);
+    const int m = (int)((idx / G) % TM);
     const int j = (int)(idx % G);
     const int4 gd = groups[grp];  // (offset index, start, tile, active)
     int n, k;
     if (!adjoint) {
-      n = 16 * gd.z + m;
+      n = TM * gd.z + m;
       k = gd.y + j;
     } else {
-      k = 16 * gd.z + m;
+      k = TM * gd.z + m;
       n = gd.y + j;
     }
     pack[idx] = cvt<T>(table_value(gd.x, n, k, nz, nt, colidx, lo, off, band));
@@ -251,28 +252,34 @@ __global__ void k_block_scale(int n_off, int nz, const int* __restrict__ colidx,
 }
 
 // FP8 pack: entries are e4m3(value / scale) with the scale of the entry's (offset, 16-depth
-// block); every K-group lies inside one block, so it carries one scale (gscale, 0 when empty).
-__global__ void k_pack_fp8(long long total, int G, bool adjoint, const int4* __restrict__ groups,
-                           int nz, int nt, const int* __restrict__ colidx,
-                           const int* __restrict__ lo, const long long* __restrict__ off,
-                           const double* __restrict__ band, const float* __restrict__ bscale,
-                           uint8_t* __restrict__ pack, float* __restrict__ gscale) {
+// block).  The 16 rows of each half of a K-group lie inside one block (forward: the group's
+// G depths; adjoint: the half's 16 depths), so each (K-group, half) carries one scale
+// (gscale, 0 when the group is empty).
+__global__ void k_pack_fp8(long long total, int G, int TM, bool adjoint,
+                           const int4* __restrict__ groups, int nz, int nt,
+                           const int* __restrict__ colidx, const int* __restrict__ lo,
+                           const long long* __restrict__ off, const double* __restrict__ band,
+                           const float* __restrict__ bscale, uint8_t* __restrict__ pack,
+                           float* __restrict__ gscale) {
   const int nblk = (nz + 15) / 16;
+  const int NH = TM / 16;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const long long grp = idx / (16 * G);
-    const int m = (int)((idx / G) % 16);
+    const long long grp = idx / ((long long)TM * G);
+    const int m = (int)((idx / G) % TM);
     const int j = (int)(idx % G);
+    const int h = m / 16;
     const int4 gd = groups[grp];
-    const int kblk = adjoint ? gd.z : gd.y / 16;
+    // rows past nz (last adjoint tile) hold zeros; their half uses the last block's scale
+    const int kblk = min(nblk - 1, adjoint ? (TM * gd.z) / 16 + h : gd.y / 16);
     const float sc = gd.x >= 0 ? bscale[(long long)gd.x * nblk + kblk] : 0.0f;
-    if (m == 0 && j == 0) gscale[grp] = sc;
+    if (m % 16 == 0 && j == 0) gscale[grp * NH + h] = sc;
     int n, k;
     if (!adjoint) {
-      n = 16 * gd.z + m;
+      n = TM * gd.z + m;
       k = gd.y + j;
     } else {
-      k = 16 * gd.z + m;
+      k = TM * gd.z + m;
       n = gd.y + j;
     }
     const double v = table_value(gd.x, n, k, nz, nt, colidx, lo, off, band);
@@ -304,10 +311,10 @@ PadGeom pad_geom(const aroam_grid& g, int L, int BR = 1, int BC = 16, int CH = 0
 
 // Mark the G-aligned runs of the inner axis that meet some column's band inside output
 // tile t for offset oi (hit[q] = 1 for run q).  Returns whether any run was hit.
-bool tile_hits(const Model& m, bool adjoint, int G, int t, int oi, std::vector<char>& hit) {
+bool tile_hits(const Model& m, bool adjoint, int G, int TM, int t, int oi, std::vector<char>& hit) {
   const int nz = m.grid.nz;
   const int out_len = adjoint ? nz : m.grid.nt;
-  const int r0 = kTile * t, r1 = std::min(out_len, r0 + kTile) - 1;
+  const int r0 = TM * t, r1 = std::min(out_len, r0 + TM) - 1;
   std::fill(hit.begin(), hit.end(), 0);
   bool any = false;
   if (!adjoint) {
@@ -352,7 +359,7 @@ int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes
     lay.h_tile_start[t] = (int)(groups.size() / kLaneGroups);
     for (int oi = 0; oi < m.n_off; ++oi) {
       const int dy = oi / W - K, dx = oi % W - K;
-      if (!tile_hits(m, adjoint, G, t, oi, hit)) continue;
+      if (!tile_hits(m, adjoint, G, kTile, t, oi, hit)) continue;
       for (size_t q = 0; q < hit.size(); ++q) {
         if (!hit[q]) continue;
         const int start = (int)q * G;
@@ -387,11 +394,12 @@ int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes
 // not hold (one row when the offset steps by one).  The row range to load is stored per unit
 // as [lo, hi) in patch-relative padded rows G = row offset + K + r.  A null K-group reads
 // staged column 0 and multiplies zero table entries.
-int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int BC, int esize,
-                        Layout& lay, size_t& bytes) {
+int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int BR, int BC,
+                        int esize, Layout& lay, size_t& bytes) {
   const aroam_grid& g = m.grid;
   const int K = m.K, W = 2 * K + 1, nz = g.nz, nt = g.nt;
   lay.G = G;
+  lay.TM = TM;
   lay.staged = true;
   lay.CH = CH;
   lay.BR = BR;
@@ -399,7 +407,7 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int
   lay.NCOL = BC + 2 * K;
   lay.CS = CH + 16 / esize;  // 16 bytes of padding per column spread the LDS banks
   lay.out_len = adjoint ? nz : nt;
-  lay.n_tiles = (int)ceil_div(lay.out_len, kTile);
+  lay.n_tiles = (int)ceil_div(lay.out_len, TM);
   lay.in = pad_geom(g, adjoint ? nt : nz, BR, BC, CH);
   lay.lds_bytes = (size_t)BR * lay.NCOL * lay.CS * esize;
   const int inner = adjoint ? nt : nz;
@@ -419,7 +427,7 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int
     for (int a = 0; a < W; ++a) {
       // input row offset: +dy for the forward, -dy for the adjoint; slot = offset + K
       const int slot = adjoint ? (W - 1 - a) : a;
-      for (int b = 0; b < W; ++b) dx_any[b] = tile_hits(m, adjoint, G, t, a * W + b, hits[b]);
+      for (int b = 0; b < W; ++b) dx_any[b] = tile_hits(m, adjoint, G, TM, t, a * W + b, hits[b]);
       for (int b = 0; b < W; ++b) {
         if (!dx_any[b]) continue;
         const int col = adjoint ? (W - 1 - b) : b;  // input column offset + K
@@ -456,7 +464,7 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int
   tile_units[lay.n_tiles] = (int)units.size();
   lay.n_units = (long long)units.size();
   lay.n_bundles = (long long)groups.size() / kLaneGroups;
-  lay.mac_exec = lay.n_bundles * kLaneGroups * kTile * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
+  lay.mac_exec = lay.n_bundles * kLaneGroups * TM * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
   AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
               "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
   AROAM_TRY(alloc_copy(&lay.d_tile_units, tile_units, bytes));
@@ -471,13 +479,13 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int CH, int BR, int
 template <typename T>
 int pack_dtype(const Model& m, const Layout& lay, bool adjoint, Pack& p, hipStream_t st,
                size_t& bytes) {
-  const long long total = lay.n_bundles * kLaneGroups * kTile * lay.G;
+  const long long total = lay.n_bundles * kLaneGroups * lay.TM * lay.G;
   p.bytes = std::max<long long>(1, total) * sizeof(T);
   AROAM_HIP(hipMalloc(&p.d, p.bytes));
   bytes += p.bytes;
   if (total > 0) {
     const int blocks = (int)std::min<long long>(ceil_div(total, 256), 1 << 16);
-    hipLaunchKernelGGL(k_pack<T>, dim3(blocks), dim3(256), 0, st, total, lay.G, adjoint,
+    hipLaunchKernelGGL(k_pack<T>, dim3(blocks), dim3(256), 0, st, total, lay.G, lay.TM, adjoint,
                        lay.d_groups, m.grid.nz, m.grid.nt, m.d_colidx, m.d_lo, m.d_off,
                        m.d_band, (T*)p.d);
     AROAM_HIP(hipGetLastError());
@@ -488,15 +496,16 @@ int pack_dtype(const Model& m, const Layout& lay, bool adjoint, Pack& p, hipStre
 int pack_fp8(const Model& m, const Layout& lay, bool adjoint, const float* bscale, Pack& p,
              hipStream_t st, size_t& bytes) {
   const long long n_groups = lay.n_bundles * kLaneGroups;
-  const long long total = n_groups * kTile * lay.G;
+  const long long n_scales = n_groups * (lay.TM / 16);
+  const long long total = n_groups * lay.TM * lay.G;
   p.bytes = std::max<long long>(1, total);
   AROAM_HIP(hipMalloc(&p.d, p.bytes));
-  AROAM_HIP(hipMalloc((void**)&p.d_scale, std::max<long long>(1, n_groups) * sizeof(float)));
-  p.bytes += std::max<long long>(1, n_groups) * sizeof(float);
+  AROAM_HIP(hipMalloc((void**)&p.d_scale, std::max<long long>(1, n_scales) * sizeof(float)));
+  p.bytes += std::max<long long>(1, n_scales) * sizeof(float);
   bytes += p.bytes;
   if (total > 0) {
     const int blocks = (int)std::min<long long>(ceil_div(total, 256), 1 << 16);
-    hipLaunchKernelGGL(k_pack_fp8, dim3(blocks), dim3(256), 0, st, total, lay.G, adjoint,
+    hipLaunchKernelGGL(k_pack_fp8, dim3(blocks), dim3(256), 0, st, total, lay.G, lay.TM, adjoint,
                        lay.d_groups, m.grid.nz, m.grid.nt, m.d_colidx, m.d_lo, m.d_off, m.d_band,
                        bscale, (uint8_t*)p.d, p.d_scale);
     AROAM_HIP(hipGetLastError());
@@ -658,8 +667,8 @@ int build_impl(Model& m, hipStream_t st) {
   AROAM_TRY(build_layout(m, true, 4, m.g4a, bytes));
   AROAM_TRY(pack_dtype<double>(m, m.g4f, false, m.fwd_pack[AROAM_FP64], st, bytes));
   AROAM_TRY(pack_dtype<double>(m, m.g4a, true, m.adj_pack[AROAM_FP64], st, bytes));
-  AROAM_TRY(build_staged_layout(m, false, 4, 16, kPatchRows, kPatchCols, 4, m.s4f, bytes));
-  AROAM_TRY(build_staged_layout(m, true, 4, 16, kPatchRows, kPatchCols, 4, m.s4a, bytes));
+  AROAM_TRY(build_staged_layout(m, false, 4, kTile, 16, kPatchRows, kPatchCols, 4, m.s4f, bytes));
+  AROAM_TRY(build_staged_layout(m, true, 4, kTile, 16, kPatchRows, kPatchCols, 4, m.s4a, bytes));
   AROAM_TRY(pack_dtype<float>(m, m.s4f, false, m.fwd_pack[AROAM_FP32], st, bytes));
   AROAM_TRY(pack_dtype<float>(m, m.s4a, true, m.adj_pack[AROAM_FP32], st, bytes));
   m.dtype_mask = (1u << AROAM_FP64) | (1u << AROAM_FP32);
@@ -696,8 +705,11 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipSt
     const bool want8 = (mask & ((1u << AROAM_BF16) | (1u << AROAM_FP8E4M3))) != 0;
     size_t bytes = 0;
     if (want8) {
-      rc = build_staged_layout(*m, false, 8, 32, kPatchRows, kPatchCols, 2, m->s8f, bytes);
-      if (!rc) rc = build_staged_layout(*m, true, 8, 32, kPatchRows, kPatchCols, 2, m->s8a, bytes);
+      rc = build_staged_layout(*m, false, 8, kTileRows8, 32, kPatchRows, kPatchCols, 2, m->s8f,
+                               bytes);
+      if (!rc)
+        rc = build_staged_layout(*m, true, 8, kTileRows8, 32, kPatchRows, kPatchCols, 2, m->s8a,
+                                 bytes);
     }
     if (!rc && (mask & (1u << AROAM_BF16))) {
       rc = pack_dtype<uint16_t>(*m, m->s8f, false, m->fwd_pack[AROAM_BF16], st, bytes);
