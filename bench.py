@@ -44,6 +44,23 @@ def kernel_times(model, dtype, x, s, reps):
     return out
 
 
+def profiled_traffic(dtype, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the apply kernels have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "apply_counters.json")
+    src = os.path.join(ROOT, "paper_2009_10173_amd", "csrc", "apply.hip")
+    try:
+        prof = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if prof.get("apply_hip_sha256") != sha:
+        return None
+    k = prof.get("kernels", {}).get(f"apply {dtype} {kernel}")
+    return None if k is None else k["bytes"]
+
+
 def cpu_baseline(cfg, mac_full, depths=(40, 41, 86, 87)):
     """The FP64 oracle's A + A^T pair on a bounded sample of the same workload: the full scan
     grid and footprint restricted to a few depth slabs, scaled to full-workload pairs/s by the
@@ -187,7 +204,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": f"{dom} ({args.dtype} MFMA)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "issued_frac": mfma_issued / peak,
-                     "traffic": None},
+                     "traffic": profiled_traffic(args.dtype, dom)},
     }
     # reduced precision with refinement on the same workload: BF16 applies, FP32 residuals
     log("BF16-refined reconstruction (2 sweeps)")
