@@ -26,10 +26,15 @@ def log(msg):
 
 
 def kernel_times(model, dtype, x, s, reps):
-    """Average duration (ms) of one forward and one adjoint launch, timed with HIP events on
-    the stream the library launches on (torch's current stream)."""
+    """Average duration (ms) of one forward and one adjoint launch on dense Gaussian vectors
+    (like the solver's Krylov vectors; x and s give the shapes), timed with HIP events on the
+    stream the library launches on (torch's current stream)."""
     import torch
     st = torch.cuda.current_stream()
+    gen = torch.Generator(device=x.device)
+    gen.manual_seed(1234)
+    x = torch.randn(x.shape, generator=gen, device=x.device, dtype=x.dtype)
+    s = torch.randn(s.shape, generator=gen, device=s.device, dtype=s.dtype)
     out = {}
     for name, fn, arg in (("forward", model.forward, x), ("adjoint", model.adjoint, s)):
         fn(arg, dtype)
