@@ -196,6 +196,37 @@ __device__ __forceinline__ void stage_prefetch(const StagedArgs& a, const T* __r
   }
 }
 
+// MFMAs of one bundle: the NT position fragments are read from LDS, each of the MH table
+// fragments multiplies all of them.
+template <typename T, bool FP8A, int MH, int NT>
+__device__ __forceinline__ void bundle_mfma(const AFrag<T, FP8A, MH>& f, const T* lds,
+                                            const int (&lbase)[NT], floatx4 (&acc)[MH][NT]) {
+  u32x4 xraw[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) xraw[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + f.mo);
+#pragma unroll
+  for (int h = 0; h < MH; ++h) {
+    u32x4 araw;
+    if constexpr (FP8A) araw = decode_fp8(f.v[h], f.sc[h]);
+    else araw = f.v[h];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if constexpr (sizeof(T) == 4) {
+        const floatx4 av = __builtin_bit_cast(floatx4, araw);
+        const floatx4 xv = __builtin_bit_cast(floatx4, xraw[t]);
+        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[h][t], 0, 0, 0);
+        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[h][t], 0, 0, 0);
+        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[h][t], 0, 0, 0);
+        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[h][t], 0, 0, 0);
+      } else {
+        const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+        const bf16x8 xv = __builtin_bit_cast(bf16x8, xraw[t]);
+        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[h][t], 0, 0, 0);
+      }
+    }
+  }
+}
+
 // LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 rows) and one patch
 // of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT 16-position
 // tiles.  The tile's bundles are grouped into stage units (chunk, input row offset).  The LDS
@@ -235,18 +266,17 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
     u32x4 pf[PF];
     int pf_off[PF];
     stage_prefetch<T, BR, PF>(a, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
-    // table-fragment ring over the tile's whole bundle range
-    const int B1 = a.units[u1 - 1].w;
-    int bnext = a.units[u0].z;
+    // table fragments stream through a ring of PD slots per stage unit, unrolled so that
+    // every slot stays in fixed registers (shifting a ring would move registers that loads
+    // in flight still target, which forces full waits)
     AFrag<T, FP8A, MH> ring[PD];
-#pragma unroll
-    for (int j = 0; j < PD; ++j) {
-      if (bnext < B1) load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, bnext, g, n, ring[j]);
-      ++bnext;
-    }
     for (int u = u0; u < u1; ++u) {
       const int4 U = a.units[u];
       const int2 Rr = a.urows[u];
+      // slot j holds bundle U.z + j (mod PD); the first loads overlap the staging below
+#pragma unroll
+      for (int j = 0; j < PD; ++j)
+        load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(U.z + j, U.w - 1), g, n, ring[j]);
       __syncthreads();  // every wave is done reading the rows this unit replaces
 #pragma unroll
       for (int i = 0; i < PF; ++i)
@@ -280,35 +310,14 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
         const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
         lbase[t] = (((r + R) % BR) * a.NCOL + c) * a.CS;
       }
-      for (int b = U.z; b < U.w; ++b) {
-        const AFrag<T, FP8A, MH> cur = ring[0];
+      for (int b0 = U.z; b0 < U.w; b0 += PD) {
 #pragma unroll
-        for (int j = 0; j + 1 < PD; ++j) ring[j] = ring[j + 1];
-        if (bnext < B1) load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, bnext, g, n, ring[PD - 1]);
-        ++bnext;
-        u32x4 xraw[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) xraw[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + cur.mo);
-#pragma unroll
-        for (int h = 0; h < MH; ++h) {
-          u32x4 araw;
-          if constexpr (FP8A) araw = decode_fp8(cur.v[h], cur.sc[h]);
-          else araw = cur.v[h];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            if constexpr (sizeof(T) == 4) {
-              const floatx4 av = __builtin_bit_cast(floatx4, araw);
-              const floatx4 xv = __builtin_bit_cast(floatx4, xraw[t]);
-              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[h][t], 0, 0, 0);
-              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[h][t], 0, 0, 0);
-              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[h][t], 0, 0, 0);
-              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[h][t], 0, 0, 0);
-            } else {
-              const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-              const bf16x8 xv = __builtin_bit_cast(bf16x8, xraw[t]);
-              acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[h][t], 0, 0, 0);
-            }
-          }
+        for (int j = 0; j < PD; ++j) {
+          if (b0 + j < U.w) bundle_mfma<T, FP8A, MH, NT>(ring[j], lds, lbase, acc);
+          // refill unconditionally (clamped to the unit's last bundle) so that the number of
+          // loads in flight is fixed and the waits can count them
+          load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(b0 + j + PD, U.w - 1), g, n,
+                              ring[j]);
         }
       }
     }
