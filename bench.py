@@ -3,7 +3,8 @@
 offsets, 50 iterations).  One step = one full reconstruction (50 iterations = 50 A + 50 A^T
 applies plus the initial A^T, with the fused FP64 vector work).  Prints one JSON line.
 
-Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16] [--no-cpu-baseline]
+Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16|fp8]
+                       [--workload vessels200|vessels400] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -18,6 +19,8 @@ if ROOT not in sys.path:
 
 METRIC = "A+Aᵀ applies/s (TMAC/s, % MFMA peak); recon p50/p99 latency vs plain FP32"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp64": 78.6}
+# peak of the MFMA each apply dtype issues: the e4m3 table is decoded to BF16 in registers
+ISSUE_PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 2500.0, "fp64": 78.6}
 DTYPE_TAG = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8", "fp64": "f64"}
 
 
@@ -66,10 +69,10 @@ def profiled_traffic(dtype, kernel):
     return None if k is None else k["bytes"]
 
 
-def cpu_baseline(cfg, mac_full, depths=(40, 41, 86, 87)):
+def cpu_baseline(cfg, mac_full, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
     """The FP64 oracle's A + A^T pair on a bounded sample of the same workload: the full scan
-    grid and footprint restricted to a few depth slabs, scaled to full-workload pairs/s by the
-    ratio of algorithmic MACs."""
+    grid and footprint restricted to a few depth slabs (at the given fractions of the depth
+    range), scaled to full-workload pairs/s by the ratio of algorithmic MACs."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -77,10 +80,11 @@ def cpu_baseline(cfg, mac_full, depths=(40, 41, 86, 87)):
     from oracle import model as omodel
     from oracle import operators as oops
     g = cfg["grid"]
-    ks = list(depths)
+    ks = [int(f * g["nz"]) for f in depth_fracs]
     t0 = time.time()
-    H = omodel.build_table(cfg["sensor"], g, depths=ks)[:, :, ks, :]
+    H = omodel.build_depth_slabs(cfg["sensor"], g, ks)
     t_table = time.time() - t0
+    log(f"oracle table for depth slabs {ks}: {t_table:.1f} s")
     nzr = H != 0                                  # [dy, dx, slab, n]
     present = nzr.any(axis=-1)
     first = np.argmax(nzr, axis=-1)
@@ -99,12 +103,14 @@ def cpu_baseline(cfg, mac_full, depths=(40, 41, 86, 87)):
         oops.forward(H, x)
         oops.adjoint(H, y)
         times.append(time.time() - t0)
+        log(f"oracle A+A^T pair on the sample: {times[-1]:.1f} s")
     t_pair = min(times)
     threads = max([d.get("num_threads", 1) for d in threadpool_info()
                    if d.get("user_api") == "blas"] or [1])
     frac = mac_sample / mac_full
     return dict(value=frac / t_pair, unit="A+A^T pairs/s", cores=int(threads), kind="oracle",
-                sample=(f"FP64 oracle A+A^T pair on depth slabs {ks} of the full 200x200 scan "
+                sample=(f"FP64 oracle A+A^T pair on depth slabs {ks} of the full "
+                        f"{g['nx']}x{g['ny']} scan "
                         f"({100 * frac:.2f}% of the algorithmic MACs), {t_pair:.2f} s per sample "
                         f"pair, scaled by the MAC ratio; table build for the slabs "
                         f"{t_table:.1f} s not included"))
@@ -116,7 +122,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="vessels200")
-    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=12,
@@ -141,7 +147,8 @@ def main():
     log(f"building model {args.workload}")
     torch.cuda.synchronize()
     t0 = time.time()
-    model = P.Model(cfg["sensor"], g, dtypes=("fp32", "bf16"))
+    lo = "fp8" if args.dtype == "fp8" else "bf16"    # inner precision of the refined leg
+    model = P.Model(cfg["sensor"], g, dtypes=tuple(sorted({"fp32", args.dtype, lo})))
     torch.cuda.synchronize()
     t_build = time.time() - t0
     info = model.info()
@@ -179,7 +186,7 @@ def main():
     flops = 2.0 * info["mac_alg"]
     achieved = flops / (kt[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.dtype]
-    mfma_issued = 2.0 * mac_exec / (kt[dom] * 1e-3) / 1e12
+    mfma_issued = 2.0 * mac_exec / (kt[dom] * 1e-3) / 1e12 / ISSUE_PEAK[args.dtype]
     result = {
         "metric": METRIC,
         "value": pairs_s,
@@ -196,7 +203,8 @@ def main():
         "config": {"workload": (f"{args.workload}: LSQR-Tikhonov {iters} its, scan "
                                 f"{g['nx']}x{g['ny']} at {g['step_m'] * 1e6:g} um, voxels "
                                 f"{g['nx']}x{g['ny']}x{g['nz']}, Nt {g['nt']}, cone footprint "
-                                f"K={g['k_half']}, 40 curved-tube phantom, 20 dB"),
+                                f"K={g['k_half']}, {cfg['phantom']['n']} curved-tube phantom, "
+                                f"{cfg['snr_db']:g} dB"),
                    "solver": "lsqr", "iters": iters},
         "tmac_s": 2.0 * info["mac_alg"] * pairs_s / 1e12,
         "recon_ms_p50": float(np.percentile(lat, 50) * 1e3),
@@ -206,30 +214,34 @@ def main():
                  "adjoint": info["mac_alg"] / info["mac_exec_adj"][di]},
         "table_build_s": t_build,
         "lambda": sinfo["lam"],
-        "roofline": {"bound": "mfma", "kernel": f"{dom} ({args.dtype} MFMA)",
+        "roofline": {"bound": "mfma", "kernel": (f"{dom} (e4m3 table, bf16 MFMA)" if args.dtype == "fp8"
+                                else f"{dom} ({args.dtype} MFMA)"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "issued_frac": mfma_issued / peak,
+                     "frac": achieved / peak, "issued_frac": mfma_issued,
                      "traffic": profiled_traffic(args.dtype, dom)},
     }
-    # reduced precision with refinement on the same workload: BF16 applies, FP32 residuals
-    log("BF16-refined reconstruction (2 sweeps)")
-    model.solve_lsqr(s, lam=-1.0, iters=iters, inner="bf16", outer="fp32", refine_sweeps=2)
+    # reduced precision with refinement on the same workload: BF16 (FP8 when the main leg is
+    # FP8) applies, FP32 residuals, two sweeps
+    log(f"{lo}-refined reconstruction (2 sweeps)")
+    x32 = x if args.dtype == "fp32" else model.solve_lsqr(s, lam=-1.0, iters=iters)[0]
+    model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32", refine_sweeps=2)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    xr, rinfo = model.solve_lsqr(s, lam=-1.0, iters=iters, inner="bf16", outer="fp32",
+    xr, rinfo = model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32",
                                  refine_sweeps=2)
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t1
-    diff = ((xr - x).norm() / x.norm()).item()
-    kt_bf16 = kernel_times(model, "bf16", x0, s, args.kernel_reps)
-    result["bf16_refined"] = {
+    diff = ((xr - x32).norm() / x32.norm()).item()
+    kt_lo = kernel_times(model, lo, x0, s, args.kernel_reps)
+    li = P.DTYPES[lo]
+    result[f"{lo}_refined"] = {
         "recon_ms": t_ref * 1e3, "sweeps": 2,
         "pairs_per_s": ((iters + 0.5) * 3 + 2 + 0.5) / t_ref,
         "rel_diff_vs_fp32_recon": diff,
-        "kernel_ms": kt_bf16,
-        "issued_frac_bf16": {k: 2.0 * (info["mac_exec"][2] if k == "forward" else
-                                       info["mac_exec_adj"][2]) / (v * 1e-3) / 1e12 / 2500.0
-                             for k, v in kt_bf16.items()},
+        "kernel_ms": kt_lo,
+        f"issued_frac_{lo}": {k: 2.0 * (info["mac_exec"][li] if k == "forward" else
+                                        info["mac_exec_adj"][li]) / (v * 1e-3) / 1e12
+                              / ISSUE_PEAK[lo] for k, v in kt_lo.items()},
     }
     if args.serve_requests > 0:
         log(f"serving leg: {args.serve_requests} mixed requests")

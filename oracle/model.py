@@ -216,6 +216,30 @@ def build_table(sensor, grid, depths=None, elems=None, workers=None):
     return H
 
 
+def build_depth_slabs(sensor, grid, depths, elems=None, workers=None):
+    """The table restricted to the listed depth indices, H[dy+K, dx+K, i, n] for depth
+    depths[i]: the same columns as `build_table`, without the zero slabs of the others."""
+    K, nt = grid["k_half"], grid["nt"]
+    if elems is None:
+        elems = sensor_elements(sensor)
+    ks = list(depths)
+    H = np.zeros((2 * K + 1, 2 * K + 1, len(ks), nt))
+    pos = {k: i for i, k in enumerate(ks)}
+    jobs = [(sensor, grid, elems, k) for k in ks]
+    if workers is None:
+        workers = min(len(ks), os.cpu_count() or 1, 16)
+    if workers > 1 and len(ks) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            for k, slab in pool.imap_unordered(_depth_slab, jobs):
+                H[:, :, pos[k], :] = slab
+    else:
+        for job in jobs:
+            k, slab = _depth_slab(job)
+            H[:, :, pos[k], :] = slab
+    return H
+
+
 def table_columns_mac(H):
     """Number of nonzero entries per (offset, depth) column: nnz counts for the work model."""
     return np.count_nonzero(H, axis=-1)

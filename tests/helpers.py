@@ -51,3 +51,20 @@ def rel_max(a, b):
     a = np.asarray(a, dtype=np.float64).ravel()
     b = np.asarray(b, dtype=np.float64).ravel()
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _window(lo, w, n, K):
+    """Sub-grid [a, b) that holds every point within K of the window [lo, lo + w), clipped to
+    the grid (outside which the model is zero), and the window's start inside it."""
+    a, b = max(0, lo - K), min(n, lo + w + K)
+    return a, b, lo - a
+
+
+def window_apply(op, Hs, v, y0, x0, w):
+    """The oracle's forward or adjoint at the lateral window [y0, y0+w) x [x0, x0+w) of a
+    full grid: both operators only reach K offsets, so they run on the window's K-halo."""
+    K = (Hs.shape[0] - 1) // 2
+    ya, yb, oy = _window(y0, w, v.shape[0], K)
+    xa, xb, ox = _window(x0, w, v.shape[1], K)
+    out = op(Hs, v[ya:yb, xa:xb])
+    return out[oy:oy + w, ox:ox + w]

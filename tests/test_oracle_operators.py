@@ -143,3 +143,25 @@ def test_shift_superposition(tiny):
     sup = s + np.roll(s, shift, axis=1)
     inner = (slice(None), slice(shift, g["nx"] - 1))
     assert np.max(np.abs(s2[inner] - sup[inner])) <= 1e-13 * np.max(np.abs(s2))
+
+
+def test_depth_slabs_and_windows_match_full_oracle():
+    """The two shortcuts the full-size parity tests use: the table restricted to a few depth
+    slabs equals those slabs of the full table, and an apply on a window's K-halo equals the
+    full-grid apply at the window (interior and edge windows)."""
+    from tests.helpers import window_apply
+    cfg = W.config("tiny")
+    g = dict(cfg["grid"], nx=20, ny=18, k_half=5, footprint_mode=1)
+    H = model.build_table(cfg["sensor"], g)
+    ks = [3, 17, 30]
+    Hs = model.build_depth_slabs(cfg["sensor"], g, ks, workers=1)
+    assert np.array_equal(Hs, H[:, :, ks, :])
+    rng = W.rng(5)
+    x = rng.standard_normal((g["ny"], g["nx"], g["nz"]))
+    y = rng.standard_normal((g["ny"], g["nx"], g["nt"]))
+    s_full, x_full = operators.forward(H, x), operators.adjoint(H, y)
+    for y0, x0, w in ((6, 7, 6), (0, 13, 7), (12, 0, 6)):
+        s_w = window_apply(operators.forward, H, x, y0, x0, w)
+        x_w = window_apply(operators.adjoint, H, y, y0, x0, w)
+        assert np.allclose(s_w, s_full[y0:y0 + w, x0:x0 + w], rtol=0, atol=1e-13 * np.abs(s_full).max())
+        assert np.allclose(x_w, x_full[y0:y0 + w, x0:x0 + w], rtol=0, atol=1e-13 * np.abs(x_full).max())

@@ -57,6 +57,13 @@ CONFIGS = {
                        phantom=dict(kind="curved", n=200, r_um=(5, 25), amp=(0.3, 1.0)),
                        snr_db=20.0, solver=dict(kind="lsqr", iters=50, lam_rule="l2",
                                                 sweeps=2)),
+    # Standalone 64x64 window problem at the fine step and footprint rule of vessels400
+    # (5 um, K = 40 cone), with the depth range cut to +-80 um (Nt = 4 Nz) so that the CPU
+    # oracle can run the FP8 refinement schedule; tube count scaled by area.
+    "window400": dict(sensor=SENSOR_4MM, grid=grid(64, 5e-6, 32, 5e-6, 128, 40, 1),
+                      phantom=dict(kind="curved", n=5, r_um=(5, 25), amp=(0.3, 1.0)),
+                      snr_db=20.0, solver=dict(kind="lsqr", iters=50, lam_rule="l2",
+                                               sweeps=2)),
     # Mid-size test case: ragged in every tiled dimension, cone footprint that cuts corners.
     "mid": dict(sensor=SENSOR_4MM, grid=grid(23, 10e-6, 40, 10e-6, 200, 12, 1, ny=19),
                 phantom=dict(kind="curved", n=4, r_um=(5, 20), amp=(0.3, 1.0)),
