@@ -10,6 +10,8 @@ enables optoacoustic microscopy beyond the acoustic diffraction limit"):
                        translational symmetry of the Methods section on scanning symmetries).
 * `oracle.operators` - the matrix-vector products A_s u and A_s^T v (Methods, scanning
                        symmetries) and a brute-force dense A_s on tiny grids (Eq. 2-4).
+* `oracle.filters`   - the band-pass FIR applied to signals and model columns before
+                       inversion (Results; Methods, in vivo imaging).
 * `oracle.solvers`   - LSQR for Tikhonov (Eq. 5-6), FISTA with soft-thresholding for L1
                        (Eq. 5, 7), the power iteration for FISTA's Lipschitz constant, and the
                        residual-correction refinement schedules.
@@ -24,4 +26,4 @@ Parity pins (what fixes each function independently of itself) live in
 listed as "parity unpinned": the footprint rule's radius factor (a model-definition
 choice) and the physical fidelity of the point-voxel / Gaussian-EIR reading.
 """
-from . import model, operators, solvers  # noqa: F401
+from . import filters, model, operators, solvers  # noqa: F401
