@@ -83,13 +83,17 @@ typedef struct {
 /* Sizes and work figures of a built model. */
 typedef struct {
   long long n_columns;   /* (offset, depth) columns kept by the footprint with a non-empty window */
-  long long nnz;         /* stored band entries of the compressed table (sum of window lengths)   */
+  long long nnz;         /* band entries of the compressed table over all those columns           */
   long long mac_alg;     /* algorithmic multiply-accumulates of one apply of A (or A^T)           */
   long long mac_exec[4]; /* MACs the forward kernel issues per apply, indexed by aroam_dtype      */
   long long mac_exec_adj[4]; /* the same for the adjoint kernel                                   */
   size_t device_bytes;   /* device memory held by the model                                        */
   int n_elements;        /* sensor sub-elements M                                                  */
   unsigned dtype_mask;   /* bit (1 << dtype) set for every dtype the model was packed for          */
+  long long stored_columns; /* FP64 columns held on the device: a built model stores one column
+                             * per symmetry class of the square (H[dx,dy] = H[+-dx,+-dy] =
+                             * H[dy,dx]), an imported one every column it was given */
+  long long stored_nnz;  /* FP64 band entries held on the device                                   */
 } aroam_model_info;
 
 /* Build the compressed model (Methods, "Efficient reconstruction based on scanning
@@ -98,13 +102,62 @@ typedef struct {
  * (Eq. 1 for point voxels, summed over sub-elements per Eq. 3-4, convolved with the EIR
  * e(t) = exp(-t^2 / (2 sigma^2)) cos(2 pi f0 t); a term counts iff |tau| <= 5 sigma).  The
  * table is computed on the device in FP64 and packed into band tiles for every dtype whose
- * bit is set in dtype_mask (1 << AROAM_FP32 etc.; FP64 and FP32 are always packed).
+ * bit is set in dtype_mask (1 << AROAM_FP32 etc.; FP64 and FP32 are always packed).  The
+ * sub-element set and the footprint are invariant under the square's symmetry group (the
+ * sensor's axial symmetry), so one column per class {(+-dx, +-dy), (+-dy, +-dx)} is computed
+ * and stored, and the offsets of a class share it.
  * On success *out owns the device tables; release with aroam_model_destroy.
  * Errors: AROAM_EINVAL for NULL pointers or sizes out of range (nx, ny, nz, nt >= 1,
  * 0 <= k_half <= 256, at most 4096 sub-elements), AROAM_ENOMEM, AROAM_EDEVICE.
  * Synchronises `stream` before returning. */
 int aroam_build_model(const aroam_sensor* sensor, const aroam_grid* grid, unsigned dtype_mask,
                       void* stream, aroam_model** out);
+
+/* Build a model from a table given in HOST memory instead of from the sensor geometry: a
+ * model matrix estimated by experiment (Discussion: raster-scanning a small particle through
+ * the volume for one transducer position) or computed elsewhere.
+ *   grid    scan / voxel grids and k_half; footprint_mode is ignored (the footprint is wherever
+ *           a column has a window)
+ *   dense   [(2 k_half + 1)][(2 k_half + 1)][nz][nt] doubles, H[dy + K][dx + K][k][n] (the layout
+ *           aroam_model_export_table writes); read only, the caller keeps ownership
+ *   col_lo, col_hi  [(2 k_half + 1)][(2 k_half + 1)][nz] inclusive sample windows, -1 for an
+ *           inactive column (values outside a window are ignored); both NULL: each column's
+ *           window is its first..last nonzero sample, all-zero columns are inactive
+ * Every column is stored as given (no symmetry folding).  dtype_mask as for
+ * aroam_build_model.  Errors: AROAM_EINVAL (NULL pointers, sizes out of range, a window outside
+ * [0, nt) or only one of col_lo / col_hi given), AROAM_ENONFINITE (a non-finite value inside a
+ * window), AROAM_ENOMEM, AROAM_EDEVICE.  Synchronises `stream` before returning. */
+int aroam_import_model(const aroam_grid* grid, const double* dense, const int* col_lo,
+                       const int* col_hi, unsigned dtype_mask, void* stream, aroam_model** out);
+
+/* Band-pass filter applied along time to the signals and to every model column before the
+ * inversion (Results: 0.5-80 MHz for the simulated sub-diffraction pairs; Methods, in vivo
+ * imaging: 1-120 MHz; the filter itself is not specified there).  A zero-phase FIR designed by
+ * the window method with 2 half_taps + 1 taps:
+ *     h[d] = w[d] ((2 f_hi / fs) sinc(2 f_hi d / fs) - (2 f_lo / fs) sinc(2 f_lo d / fs)),
+ *     w[d] = 0.42 + 0.5 cos(pi d / L) + 0.08 cos(2 pi d / L)  (Blackman),  |d| <= L = half_taps,
+ * sinc(u) = sin(pi u) / (pi u), applied as y[n] = sum_d h[d] x[n - d] with x = 0 outside
+ * [0, nt).  Band edges below about fs / (2 L) are only approximated by so short a filter. */
+typedef struct {
+  double f_lo_hz, f_hi_hz;  /* band edges, 0 <= f_lo < f_hi <= fs / 2                */
+  int half_taps;            /* L, 0 <= L <= min(1024, nt - 1)                       */
+} aroam_filter;
+
+/* aroam_build_model for the filtered model F A: every column of the table is filtered along
+ * time (its window [lo, hi] grows to [lo - L, hi + L] within [0, nt)).  The model keeps the
+ * filter for aroam_filter_signals.  Errors as aroam_build_model, plus AROAM_EINVAL for a NULL
+ * or invalid filter. */
+int aroam_build_model_filtered(const aroam_sensor* sensor, const aroam_grid* grid,
+                               const aroam_filter* filter, unsigned dtype_mask, void* stream,
+                               aroam_model** out);
+
+/* s_out = F s_in for all ny * nx signals [ny][nx][nt] (device pointers, FP64 or FP32 as
+ * `dtype`, accumulated in that precision) with the filter of a model built by
+ * aroam_build_model_filtered.  Asynchronous on `stream`.  s_in and s_out must not overlap.
+ * Errors: AROAM_EINVAL (NULL pointers, in == out, a model without a filter, dtype other than
+ * FP64 / FP32), AROAM_EDEVICE. */
+int aroam_filter_signals(const aroam_model* model, int dtype, const void* s_in, void* s_out,
+                         void* stream);
 
 /* Fill *info (host pointer). */
 int aroam_model_query(const aroam_model* model, aroam_model_info* info);

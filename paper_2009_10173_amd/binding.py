@@ -35,11 +35,16 @@ class Grid(C.Structure):
                 ("k_half", C.c_int), ("footprint_mode", C.c_int)]
 
 
+class Filter(C.Structure):
+    _fields_ = [("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double), ("half_taps", C.c_int)]
+
+
 class ModelInfo(C.Structure):
     _fields_ = [("n_columns", C.c_longlong), ("nnz", C.c_longlong), ("mac_alg", C.c_longlong),
                 ("mac_exec", C.c_longlong * 4), ("mac_exec_adj", C.c_longlong * 4),
                 ("device_bytes", C.c_size_t), ("n_elements", C.c_int),
-                ("dtype_mask", C.c_uint)]
+                ("dtype_mask", C.c_uint), ("stored_columns", C.c_longlong),
+                ("stored_nnz", C.c_longlong)]
 
 
 class SolveOpts(C.Structure):
@@ -59,6 +64,12 @@ _LIB = None
 _SYMBOLS = {
     "aroam_build_model": ([C.POINTER(Sensor), C.POINTER(Grid), C.c_uint, C.c_void_p,
                            C.POINTER(C.c_void_p)], C.c_int),
+    "aroam_build_model_filtered": ([C.POINTER(Sensor), C.POINTER(Grid), C.POINTER(Filter),
+                                    C.c_uint, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "aroam_filter_signals": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
+                             C.c_int),
+    "aroam_import_model": ([C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint,
+                            C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "aroam_model_query": ([C.c_void_p, C.POINTER(ModelInfo)], C.c_int),
     "aroam_model_export_table": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "aroam_forward": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
@@ -147,13 +158,55 @@ def aroam_build_model(sensor, grid, dtype_mask, stream=None):
     return h
 
 
+def _filter(f):
+    return Filter(float(f["f_lo_hz"]), float(f["f_hi_hz"]), int(f["half_taps"]))
+
+
+def aroam_build_model_filtered(sensor, grid, filt, dtype_mask, stream=None):
+    h = C.c_void_p()
+    _check(load_library().aroam_build_model_filtered(
+        C.byref(_sensor(sensor)), C.byref(_grid(grid)), C.byref(_filter(filt)), dtype_mask,
+        _stream(stream), C.byref(h)))
+    return h
+
+
+def aroam_filter_signals(h, dtype, s_in, s_out, stream=None):
+    _check(load_library().aroam_filter_signals(h, dtype, _ptr(s_in), _ptr(s_out),
+                                               _stream(stream)))
+
+
+def aroam_import_model(grid, dense, col_lo=None, col_hi=None, dtype_mask=0, stream=None):
+    """dense: host float64 array [2K+1][2K+1][nz][nt]; col_lo / col_hi: int32 [2K+1][2K+1][nz]
+    or None.  Returns the model handle."""
+    import numpy as np
+    K, nz, nt = grid["k_half"], grid["nz"], grid["nt"]
+    W = 2 * K + 1
+    H = np.ascontiguousarray(dense, dtype=np.float64)
+    if H.shape != (W, W, nz, nt):
+        raise ValueError(f"table shape {H.shape} != {(W, W, nz, nt)}")
+    lo = hi = None
+    if col_lo is not None or col_hi is not None:
+        lo = np.ascontiguousarray(col_lo, dtype=np.int32)
+        hi = np.ascontiguousarray(col_hi, dtype=np.int32)
+        if lo.shape != (W, W, nz) or hi.shape != (W, W, nz):
+            raise ValueError("window arrays must have shape [2K+1][2K+1][nz]")
+    h = C.c_void_p()
+    _check(load_library().aroam_import_model(
+        C.byref(_grid(grid)), H.ctypes.data_as(C.c_void_p),
+        None if lo is None else lo.ctypes.data_as(C.c_void_p),
+        None if hi is None else hi.ctypes.data_as(C.c_void_p), dtype_mask, _stream(stream),
+        C.byref(h)))
+    return h
+
+
 def aroam_model_query(h):
     info = ModelInfo()
     _check(load_library().aroam_model_query(h, C.byref(info)))
     return dict(n_columns=info.n_columns, nnz=info.nnz, mac_alg=info.mac_alg,
                 mac_exec=list(info.mac_exec), mac_exec_adj=list(info.mac_exec_adj),
                 device_bytes=info.device_bytes, n_elements=info.n_elements,
-                dtype_mask=info.dtype_mask)
+                dtype_mask=info.dtype_mask, stored_columns=info.stored_columns,
+                stored_nnz=info.stored_nnz)
 
 
 def aroam_model_export_table(h, grid, dense=True):
@@ -269,15 +322,33 @@ def aroam_server_destroy(server):
 
 # --- convenience wrapper -----------------------------------------------------------------
 
+def _mask(dtypes):
+    mask = 0
+    for d in dtypes:
+        mask |= 1 << (DTYPES[d] if isinstance(d, str) else int(d))
+    return mask
+
+
 class Model:
     """A built model (device-resident tables) plus its grid; frees itself on close()."""
 
-    def __init__(self, sensor, grid, dtypes=("fp64", "fp32"), stream=None):
-        mask = 0
-        for d in dtypes:
-            mask |= 1 << (DTYPES[d] if isinstance(d, str) else int(d))
-        self.sensor, self.grid = dict(sensor), dict(grid)
-        self.handle = aroam_build_model(sensor, grid, mask, stream)
+    def __init__(self, sensor, grid, dtypes=("fp64", "fp32"), stream=None, filter=None,
+                 _handle=None):
+        self.sensor, self.grid = (None if sensor is None else dict(sensor)), dict(grid)
+        self.filter = None if filter is None else dict(filter)
+        if _handle is not None:
+            self.handle = _handle
+        elif filter is None:
+            self.handle = aroam_build_model(sensor, grid, _mask(dtypes), stream)
+        else:
+            self.handle = aroam_build_model_filtered(sensor, grid, filter, _mask(dtypes), stream)
+
+    @classmethod
+    def from_table(cls, grid, dense, col_lo=None, col_hi=None, dtypes=("fp64", "fp32"),
+                   stream=None):
+        """A model from a table given on the host (aroam_import_model)."""
+        h = aroam_import_model(grid, dense, col_lo, col_hi, _mask(dtypes), stream)
+        return cls(None, grid, _handle=h)
 
     def info(self):
         return aroam_model_query(self.handle)
@@ -317,6 +388,18 @@ class Model:
         _expect(s, self.signal_shape, self._vec_dtype(dtype))
         _expect(out, self.image_shape, self._vec_dtype(dtype))
         aroam_adjoint(self.handle, dtype, s, out, stream)
+        return out
+
+    def filter_signals(self, s, out=None, stream=None):
+        """F s with the model's band-pass filter, in the tensor's precision (FP64 or FP32)."""
+        import torch
+        if s.dtype not in (torch.float64, torch.float32):
+            raise ValueError(f"signals are filtered in float64 or float32, not {s.dtype}")
+        d = AROAM_FP64 if s.dtype == torch.float64 else AROAM_FP32
+        _expect(s, self.signal_shape, s.dtype)
+        if out is None:
+            out = torch.empty_like(s)
+        aroam_filter_signals(self.handle, d, s, out, stream)
         return out
 
     def solve_lsqr(self, s, lam=-1.0, iters=50, inner="fp32", outer=None, refine_sweeps=0,

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libaroam.so")
-SOURCES = ["capi.hip", "table.hip", "apply.hip", "solvers.hip", "serve.hip"]
+SOURCES = ["capi.hip", "table.hip", "filter.hip", "apply.hip", "solvers.hip", "serve.hip"]
 ARCH = os.environ.get("AROAM_ARCH", "gfx950")
 
 FLAGS = [

@@ -30,10 +30,10 @@ struct aroam_model {
 
 using aroam::Model;
 
-extern "C" {
+namespace {
 
-int aroam_build_model(const aroam_sensor* sensor, const aroam_grid* grid, unsigned dtype_mask,
-                      void* stream, aroam_model** out) {
+int build_handle(const aroam_sensor* sensor, const aroam_grid* grid, const aroam_filter* filter,
+                 unsigned dtype_mask, void* stream, aroam_model** out) {
   aroam::clear_error();
   if (!out) {
     aroam::set_error("NULL output handle");
@@ -41,7 +41,59 @@ int aroam_build_model(const aroam_sensor* sensor, const aroam_grid* grid, unsign
   }
   *out = nullptr;
   Model* m = nullptr;
-  int rc = aroam::build_model(sensor, grid, dtype_mask, (hipStream_t)stream, &m);
+  int rc = aroam::build_model(sensor, grid, filter, dtype_mask, (hipStream_t)stream, &m);
+  if (rc != AROAM_OK) return rc;
+  aroam_model* h = new (std::nothrow) aroam_model{m};
+  if (!h) {
+    aroam::destroy_model(m);
+    aroam::set_error("host allocation failed");
+    return AROAM_ENOMEM;
+  }
+  *out = h;
+  return AROAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+
+int aroam_build_model(const aroam_sensor* sensor, const aroam_grid* grid, unsigned dtype_mask,
+                      void* stream, aroam_model** out) {
+  return build_handle(sensor, grid, nullptr, dtype_mask, stream, out);
+}
+
+int aroam_build_model_filtered(const aroam_sensor* sensor, const aroam_grid* grid,
+                               const aroam_filter* filter, unsigned dtype_mask, void* stream,
+                               aroam_model** out) {
+  if (!filter) {
+    aroam::clear_error();
+    aroam::set_error("NULL filter");
+    return AROAM_EINVAL;
+  }
+  return build_handle(sensor, grid, filter, dtype_mask, stream, out);
+}
+
+int aroam_filter_signals(const aroam_model* model, int dtype, const void* s_in, void* s_out,
+                         void* stream) {
+  aroam::clear_error();
+  if (!model) {
+    aroam::set_error("NULL model");
+    return AROAM_EINVAL;
+  }
+  return aroam::filter_signals(*model->m, dtype, s_in, s_out, (hipStream_t)stream);
+}
+
+int aroam_import_model(const aroam_grid* grid, const double* dense, const int* col_lo,
+                       const int* col_hi, unsigned dtype_mask, void* stream, aroam_model** out) {
+  aroam::clear_error();
+  if (!out) {
+    aroam::set_error("NULL output handle");
+    return AROAM_EINVAL;
+  }
+  *out = nullptr;
+  Model* m = nullptr;
+  int rc = aroam::import_model(grid, dense, col_lo, col_hi, dtype_mask, (hipStream_t)stream, &m);
   if (rc != AROAM_OK) return rc;
   aroam_model* h = new (std::nothrow) aroam_model{m};
   if (!h) {
@@ -71,6 +123,8 @@ int aroam_model_query(const aroam_model* model, aroam_model_info* info) {
   info->device_bytes = m.device_bytes;
   info->n_elements = m.M;
   info->dtype_mask = m.dtype_mask;
+  info->stored_columns = m.n_stored;
+  info->stored_nnz = m.nnz_stored;
   return AROAM_OK;
 }
 
@@ -88,9 +142,10 @@ int aroam_model_export_table(const aroam_model* model, double* dense, int* col_l
   if (col_hi)
     for (size_t i = 0; i < ncol; ++i) col_hi[i] = m.h_hi[i];
   if (dense) {
-    std::vector<double> band((size_t)std::max<long long>(1, m.nnz));
-    if (m.nnz > 0 &&
-        hipMemcpy(band.data(), m.d_band, m.nnz * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    std::vector<double> band((size_t)std::max<long long>(1, m.nnz_stored));
+    if (m.nnz_stored > 0 &&
+        hipMemcpy(band.data(), m.d_band, m.nnz_stored * sizeof(double), hipMemcpyDeviceToHost) !=
+            hipSuccess) {
       aroam::set_error("table download failed");
       return AROAM_EDEVICE;
     }

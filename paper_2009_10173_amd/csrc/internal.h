@@ -108,27 +108,48 @@ struct Model {
   double R_mm = 0, cfs = 0;      // focal radius (mm), mm per sample
   double sigma = 0, omega = 0;   // EIR envelope (samples), carrier (rad/sample)
   double step_mm = 0, dz_mm = 0;
-  long long n_columns = 0, nnz = 0, mac_alg = 0;
+  long long n_columns = 0, nnz = 0, mac_alg = 0;  // over all footprint columns
+  long long n_stored = 0, nnz_stored = 0;         // columns / band entries held on the device
   std::vector<int> h_lo, h_hi;   // [n_off][nz], -1 where inactive
-  std::vector<long long> h_off;  // [n_columns + 1] band offsets of active columns
-  std::vector<int> h_colidx;     // [n_off][nz] -> active column index or -1
+  std::vector<long long> h_off;  // [n_stored + 1] band offsets of the stored columns
+  std::vector<int> h_colidx;     // [n_off][nz] -> stored column index or -1
   // device tables
-  double* d_band = nullptr;      // FP64 band values [nnz]
+  double* d_band = nullptr;      // FP64 band values [nnz_stored]
   int* d_colidx = nullptr;       // [n_off][nz]
-  int* d_lo = nullptr;           // [n_columns]
-  long long* d_off = nullptr;    // [n_columns + 1]
+  int* d_lo = nullptr;           // [n_stored]
+  long long* d_off = nullptr;    // [n_stored + 1]
   Layout g4f, g4a;               // direct form, G = 4: FP64 forward / adjoint
   Layout s4f, s4a;               // LDS-staged, G = 4: FP32
   Layout s8f, s8a;               // LDS-staged, G = 8: BF16 / FP8
   Pack fwd_pack[4], adj_pack[4]; // indexed by aroam_dtype
+  // band-pass filter applied along time to the columns (and, by the caller, to the signals)
+  bool filtered = false;
+  aroam_filter filter{};
+  int fir_L = 0;
+  std::vector<double> fir_taps;  // h[-L..L]
+  double* d_fir_taps = nullptr;  // h[-L..L]
+  double* d_fir_pad64 = nullptr; // zero-padded taps for the signal kernel, FP64 and FP32
+  float* d_fir_pad32 = nullptr;
   unsigned dtype_mask = 0;
   size_t device_bytes = 0;
   int device = 0;
 };
 
+// filter.hip
+std::vector<double> fir_taps(const aroam_filter& f, double fs);
+int check_filter(const aroam_filter& f, double fs, int nt);
+int setup_filter(Model& m, const aroam_filter& f);
+int filter_columns(const Model& m, const int* d_rlo, const long long* d_roff,
+                   const double* d_raw, hipStream_t st);
+int filter_signals(const Model& m, int dtype, const void* in, void* out, hipStream_t st);
+
 // table.hip
-int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipStream_t st,
-                Model** out);
+int check_grid(const aroam_grid* g);
+int finish_model(Model* m, int rc, unsigned mask, hipStream_t st, Model** out);
+int import_model(const aroam_grid* g, const double* dense, const int* col_lo,
+                 const int* col_hi, unsigned mask, hipStream_t st, Model** out);
+int build_model(const aroam_sensor* s, const aroam_grid* g, const aroam_filter* f,
+                unsigned mask, hipStream_t st, Model** out);
 void destroy_model(Model* m);
 
 // apply.hip

@@ -529,6 +529,13 @@ int pack_all_fp8(Model& m, hipStream_t st, size_t& bytes) {
   return rc;
 }
 
+int set_columns(Model& m, const std::vector<int>& foi, const std::vector<int>& fk,
+                const std::vector<int>& fsrc, const std::vector<int>& stored,
+                const std::vector<int>& src_lo, const std::vector<int>& src_hi,
+                const std::vector<int>& slo, const std::vector<long long>& soff,
+                const std::vector<double>& values, size_t& bytes);
+int pack_fp(Model& m, hipStream_t st, size_t& bytes);
+
 int build_impl(Model& m, hipStream_t st) {
   const aroam_sensor& s = m.sensor;
   const aroam_grid& g = m.grid;
@@ -551,18 +558,33 @@ int build_impl(Model& m, hipStream_t st) {
   m.step_mm = g.step_m * kMM;
   m.dz_mm = g.dz_m * kMM;
 
-  // footprint columns, in (dy, dx, k) order
-  std::vector<int> fdx, fdy, fk, foi;
+  // Footprint columns, in (dy, dx, k) order.  The sub-element set and the footprint are
+  // invariant under the square's symmetry group (the sensor's axial symmetry, Methods,
+  // scanning symmetries), so H[dx, dy] = H[+-dx, +-dy] = H[dy, dx]: only the canonical
+  // columns (cx, cy, k) with 0 <= cy <= cx are evaluated and stored, and every footprint
+  // column points at its canonical one.
+  const int Kc = K + 1;
+  std::vector<int> can_of((size_t)Kc * Kc * nz, -1);  // (cy, cx, k) -> canonical column
+  std::vector<int> cdx, cdy, ck;                      // canonical columns
+  std::vector<int> foi, fk, fcan;                     // footprint columns
   for (int a = 0; a < W; ++a)
     for (int b = 0; b < W; ++b)
-      for (int k = 0; k < nz; ++k)
-        if (in_footprint(s, g, b - K, a - K, k)) {
-          fdx.push_back(b - K);
-          fdy.push_back(a - K);
-          fk.push_back(k);
-          foi.push_back(a * W + b);
+      for (int k = 0; k < nz; ++k) {
+        if (!in_footprint(s, g, b - K, a - K, k)) continue;
+        const int ax = std::abs(b - K), ay = std::abs(a - K);
+        const int cx = std::max(ax, ay), cy = std::min(ax, ay);
+        int& ci = can_of[((size_t)cy * Kc + cx) * nz + k];
+        if (ci < 0) {
+          ci = (int)cdx.size();
+          cdx.push_back(cx);
+          cdy.push_back(cy);
+          ck.push_back(k);
         }
-  const int nf = (int)fk.size();
+        foi.push_back(a * W + b);
+        fk.push_back(k);
+        fcan.push_back(ci);
+      }
+  const int nc = (int)cdx.size();
 
   Geo geo;
   geo.step = m.step_mm;
@@ -578,12 +600,12 @@ int build_impl(Model& m, hipStream_t st) {
   geo.dz_m = g.dz_m;
 
   double *d_ex = nullptr, *d_ey = nullptr, *d_ez = nullptr, *d_eoff = nullptr, *d_area = nullptr;
-  int *d_fdx = nullptr, *d_fdy = nullptr, *d_fk = nullptr, *d_flo = nullptr, *d_fhi = nullptr;
+  int *d_cdx = nullptr, *d_cdy = nullptr, *d_ck = nullptr, *d_clo = nullptr, *d_chi = nullptr;
   size_t tmp = 0;
   int rc = AROAM_OK;
   auto cleanup = [&]() {
     (void)hipFree(d_ex); (void)hipFree(d_ey); (void)hipFree(d_ez); (void)hipFree(d_eoff); (void)hipFree(d_area);
-    (void)hipFree(d_fdx); (void)hipFree(d_fdy); (void)hipFree(d_fk); (void)hipFree(d_flo); (void)hipFree(d_fhi);
+    (void)hipFree(d_cdx); (void)hipFree(d_cdy); (void)hipFree(d_ck); (void)hipFree(d_clo); (void)hipFree(d_chi);
   };
   do {
     if ((rc = alloc_copy(&d_ex, ex, tmp))) break;
@@ -591,77 +613,148 @@ int build_impl(Model& m, hipStream_t st) {
     if ((rc = alloc_copy(&d_ez, ez, tmp))) break;
     if ((rc = alloc_copy(&d_eoff, eoff, tmp))) break;
     if ((rc = alloc_copy(&d_area, area, tmp))) break;
-    if ((rc = alloc_copy(&d_fdx, fdx, tmp))) break;
-    if ((rc = alloc_copy(&d_fdy, fdy, tmp))) break;
-    if ((rc = alloc_copy(&d_fk, fk, tmp))) break;
-    std::vector<int> zeros(nf, 0);
-    if ((rc = alloc_copy(&d_flo, zeros, tmp))) break;
-    if ((rc = alloc_copy(&d_fhi, zeros, tmp))) break;
-    if (nf > 0) {
-      hipLaunchKernelGGL(k_support, dim3((unsigned)ceil_div(nf, 128)), dim3(128), 0, st, nf,
-                         d_fdx, d_fdy, d_fk, d_ex, d_ey, d_ez, d_eoff, geo, d_flo, d_fhi);
+    if ((rc = alloc_copy(&d_cdx, cdx, tmp))) break;
+    if ((rc = alloc_copy(&d_cdy, cdy, tmp))) break;
+    if ((rc = alloc_copy(&d_ck, ck, tmp))) break;
+    std::vector<int> zeros(nc, 0);
+    if ((rc = alloc_copy(&d_clo, zeros, tmp))) break;
+    if ((rc = alloc_copy(&d_chi, zeros, tmp))) break;
+    if (nc > 0) {
+      hipLaunchKernelGGL(k_support, dim3((unsigned)ceil_div(nc, 128)), dim3(128), 0, st, nc,
+                         d_cdx, d_cdy, d_ck, d_ex, d_ey, d_ez, d_eoff, geo, d_clo, d_chi);
       if (hipGetLastError() != hipSuccess) { set_error("support kernel launch failed"); rc = AROAM_EDEVICE; break; }
     }
-    std::vector<int> flo(nf), fhi(nf);
-    if (nf > 0) {
-      if (hipMemcpyAsync(flo.data(), d_flo, nf * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipMemcpyAsync(fhi.data(), d_fhi, nf * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    std::vector<int> clo(nc), chi(nc);
+    if (nc > 0) {
+      if (hipMemcpyAsync(clo.data(), d_clo, nc * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(chi.data(), d_chi, nc * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
         set_error("support download failed");
         rc = AROAM_EDEVICE;
         break;
       }
     }
-    // active columns: footprint columns with a non-empty window
-    m.h_lo.assign((size_t)m.n_off * nz, -1);
-    m.h_hi.assign((size_t)m.n_off * nz, -1);
-    m.h_colidx.assign((size_t)m.n_off * nz, -1);
-    std::vector<int> adx, ady, ak, alo;
-    m.h_off.clear();
-    m.h_off.push_back(0);
-    m.mac_alg = 0;
-    for (int c = 0; c < nf; ++c) {
-      if (flo[c] < 0) continue;
-      const size_t key = (size_t)foi[c] * nz + fk[c];
-      m.h_lo[key] = flo[c];
-      m.h_hi[key] = fhi[c];
-      m.h_colidx[key] = (int)alo.size();
-      adx.push_back(fdx[c]);
-      ady.push_back(fdy[c]);
-      ak.push_back(fk[c]);
-      alo.push_back(flo[c]);
-      const long long len = fhi[c] - flo[c] + 1;
-      m.h_off.push_back(m.h_off.back() + len);
-      const long long pairs = (long long)std::max(0, g.ny - std::abs(fdy[c])) *
-                              std::max(0, g.nx - std::abs(fdx[c]));
-      m.mac_alg += pairs * len;
+    // stored columns: canonical columns with a non-empty window.  With a band-pass filter the
+    // stored window is the filtered one, [lo - L, hi + L] in [0, nt); the sub-element sum is
+    // first evaluated on the raw window [lo, hi].
+    const int L = m.filtered ? m.fir_L : 0;
+    std::vector<int> elo(nc, -1), ehi(nc, -1);
+    for (int c = 0; c < nc; ++c)
+      if (clo[c] >= 0) {
+        elo[c] = std::max(0, clo[c] - L);
+        ehi[c] = std::min(g.nt - 1, chi[c] + L);
+      }
+    std::vector<int> stored(nc, -1), sdx, sdy, sk, slo, rlo;
+    std::vector<long long> soff(1, 0), roff(1, 0);
+    for (int c = 0; c < nc; ++c) {
+      if (clo[c] < 0) continue;
+      stored[c] = (int)slo.size();
+      sdx.push_back(cdx[c]);
+      sdy.push_back(cdy[c]);
+      sk.push_back(ck[c]);
+      slo.push_back(elo[c]);
+      soff.push_back(soff.back() + (ehi[c] - elo[c] + 1));
+      rlo.push_back(clo[c]);
+      roff.push_back(roff.back() + (chi[c] - clo[c] + 1));
     }
-    m.n_columns = (long long)alo.size();
-    m.nnz = m.h_off.back();
-    if ((rc = alloc_copy(&m.d_colidx, m.h_colidx, bytes))) break;
-    if ((rc = alloc_copy(&m.d_lo, alo, bytes))) break;
-    if ((rc = alloc_copy(&m.d_off, m.h_off, bytes))) break;
-    const size_t band_bytes = std::max<long long>(1, m.nnz) * sizeof(double);
-    if (hipMalloc((void**)&m.d_band, band_bytes) != hipSuccess) { set_error("out of device memory for the table"); rc = AROAM_ENOMEM; break; }
-    bytes += band_bytes;
-    int *d_adx = nullptr, *d_ady = nullptr, *d_ak = nullptr;
-    if ((rc = alloc_copy(&d_adx, adx, tmp)) || (rc = alloc_copy(&d_ady, ady, tmp)) ||
-        (rc = alloc_copy(&d_ak, ak, tmp))) {
-      (void)hipFree(d_adx); (void)hipFree(d_ady); (void)hipFree(d_ak);
+    std::vector<double> no_values;
+    if ((rc = set_columns(m, foi, fk, fcan, stored, elo, ehi, slo, soff, no_values, bytes))) break;
+    int *d_sdx = nullptr, *d_sdy = nullptr, *d_sk = nullptr, *d_rlo = nullptr;
+    long long* d_roff = nullptr;
+    double* d_raw = nullptr;
+    auto free_cols = [&]() {
+      (void)hipFree(d_sdx); (void)hipFree(d_sdy); (void)hipFree(d_sk);
+      (void)hipFree(d_rlo); (void)hipFree(d_roff); (void)hipFree(d_raw);
+    };
+    if ((rc = alloc_copy(&d_sdx, sdx, tmp)) || (rc = alloc_copy(&d_sdy, sdy, tmp)) ||
+        (rc = alloc_copy(&d_sk, sk, tmp))) {
+      free_cols();
       break;
     }
-    if (m.n_columns > 0) {
-      hipLaunchKernelGGL(k_table, dim3((unsigned)m.n_columns), dim3(64), 2 * m.M * sizeof(double),
-                         st, d_adx, d_ady, d_ak, m.d_lo, m.d_off, d_ex, d_ey, d_ez, d_eoff,
-                         d_area, geo, m.d_band);
+    if (m.filtered) {
+      if ((rc = alloc_copy(&d_rlo, rlo, tmp)) || (rc = alloc_copy(&d_roff, roff, tmp))) {
+        free_cols();
+        break;
+      }
+      if (hipMalloc((void**)&d_raw, std::max<long long>(1, roff.back()) * sizeof(double)) !=
+          hipSuccess) {
+        set_error("out of device memory for the unfiltered table");
+        rc = AROAM_ENOMEM;
+        free_cols();
+        break;
+      }
+    }
+    if (m.n_stored > 0) {
+      hipLaunchKernelGGL(k_table, dim3((unsigned)m.n_stored), dim3(64), 2 * m.M * sizeof(double),
+                         st, d_sdx, d_sdy, d_sk, m.filtered ? d_rlo : m.d_lo,
+                         m.filtered ? d_roff : m.d_off, d_ex, d_ey, d_ez, d_eoff, d_area, geo,
+                         m.filtered ? d_raw : m.d_band);
       if (hipGetLastError() != hipSuccess) { set_error("table kernel launch failed"); rc = AROAM_EDEVICE; }
+      if (rc == AROAM_OK && m.filtered) rc = filter_columns(m, d_rlo, d_roff, d_raw, st);
     }
     if (rc == AROAM_OK && hipStreamSynchronize(st) != hipSuccess) { set_error("table build failed"); rc = AROAM_EDEVICE; }
-    (void)hipFree(d_adx); (void)hipFree(d_ady); (void)hipFree(d_ak);
+    free_cols();
   } while (false);
   cleanup();
   if (rc) return rc;
+  return pack_fp(m, st, bytes);
+}
 
+// Host side of the column set: the footprint columns (offset index, depth, source column)
+// point at stored columns; windows come from the source columns.  Uploads the column maps
+// and allocates the FP64 band (filled from `values` when it is not empty).
+int set_columns(Model& m, const std::vector<int>& foi, const std::vector<int>& fk,
+                const std::vector<int>& fsrc, const std::vector<int>& stored,
+                const std::vector<int>& src_lo, const std::vector<int>& src_hi,
+                const std::vector<int>& slo, const std::vector<long long>& soff,
+                const std::vector<double>& values, size_t& bytes) {
+  const aroam_grid& g = m.grid;
+  const int nz = g.nz, K = m.K;
+  m.h_lo.assign((size_t)m.n_off * nz, -1);
+  m.h_hi.assign((size_t)m.n_off * nz, -1);
+  m.h_colidx.assign((size_t)m.n_off * nz, -1);
+  m.h_off = soff;
+  m.n_columns = 0;
+  m.nnz = 0;
+  m.mac_alg = 0;
+  const int W = 2 * K + 1;
+  for (size_t i = 0; i < foi.size(); ++i) {
+    const int c = fsrc[i];
+    if (c < 0 || stored[c] < 0) continue;
+    const size_t key = (size_t)foi[i] * nz + fk[i];
+    m.h_lo[key] = src_lo[c];
+    m.h_hi[key] = src_hi[c];
+    m.h_colidx[key] = stored[c];
+    const long long len = src_hi[c] - src_lo[c] + 1;
+    const int dy = foi[i] / W - K, dx = foi[i] % W - K;
+    const long long pairs = (long long)std::max(0, g.ny - std::abs(dy)) *
+                            std::max(0, g.nx - std::abs(dx));
+    m.n_columns += 1;
+    m.nnz += len;
+    m.mac_alg += pairs * len;
+  }
+  m.n_stored = (long long)slo.size();
+  m.nnz_stored = soff.back();
+  size_t tmp = 0;
+  AROAM_TRY(alloc_copy(&m.d_colidx, m.h_colidx, bytes));
+  AROAM_TRY(alloc_copy(&m.d_lo, slo, tmp));
+  AROAM_TRY(alloc_copy(&m.d_off, soff, tmp));
+  const size_t band_bytes = std::max<long long>(1, m.nnz_stored) * sizeof(double);
+  if (hipMalloc((void**)&m.d_band, band_bytes) != hipSuccess) {
+    set_error("out of device memory for the table");
+    return AROAM_ENOMEM;
+  }
+  if (!values.empty() &&
+      hipMemcpy(m.d_band, values.data(), m.nnz_stored * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    set_error("table upload failed");
+    return AROAM_EDEVICE;
+  }
+  return AROAM_OK;
+}
+
+// Band tiles of the always-packed dtypes (FP64 direct form, FP32 staged form).
+int pack_fp(Model& m, hipStream_t st, size_t& bytes) {
   // band tiles
   AROAM_TRY(build_layout(m, false, 4, m.g4f, bytes));
   AROAM_TRY(build_layout(m, true, 4, m.g4a, bytes));
@@ -677,22 +770,18 @@ int build_impl(Model& m, hipStream_t st) {
 
 }  // namespace
 
-int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipStream_t st,
-                Model** out) {
+int build_model(const aroam_sensor* s, const aroam_grid* g, const aroam_filter* f,
+                unsigned mask, hipStream_t st, Model** out) {
   AROAM_CHECK(s && g && out, AROAM_EINVAL, "NULL argument to aroam_build_model");
   *out = nullptr;
   AROAM_CHECK(s->radius_m > 0 && s->aperture_m > 0 && s->aperture_m <= 2 * s->radius_m &&
                   s->hole_m >= 0 && s->hole_m < s->aperture_m && s->f0_hz > 0 &&
                   s->frac_bw > 0 && s->n_rings >= 0 && s->n_rings <= 1000,
               AROAM_EINVAL, "invalid sensor geometry");
-  AROAM_CHECK(g->c_mps > 0 && g->fs_hz > 0 && g->step_m > 0 && g->dz_m > 0, AROAM_EINVAL,
-              "invalid grid spacing");
-  AROAM_CHECK(g->nx >= 1 && g->ny >= 1 && g->nz >= 1 && g->nt >= 1 && g->nx <= 65536 &&
-                  g->ny <= 65536 && g->nz <= 65536 && g->nt <= 65536,
-              AROAM_EINVAL, "grid sizes out of range");
-  AROAM_CHECK(g->k_half >= 0 && g->k_half <= 256, AROAM_EINVAL, "k_half out of range");
+  AROAM_TRY(check_grid(g));
   AROAM_CHECK(g->footprint_mode == 0 || g->footprint_mode == 1, AROAM_EINVAL,
               "footprint_mode must be 0 or 1");
+  if (f) AROAM_TRY(check_filter(*f, g->fs_hz, g->nt));
   Model* m = new (std::nothrow) Model();
   AROAM_CHECK(m, AROAM_ENOMEM, "host allocation failed");
   m->sensor = *s;
@@ -700,7 +789,80 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipSt
   m->K = g->k_half;
   m->n_off = (2 * g->k_half + 1) * (2 * g->k_half + 1);
   (void)hipGetDevice(&m->device);
-  int rc = build_impl(*m, st);
+  int rc = AROAM_OK;
+  if (f) rc = setup_filter(*m, *f);
+  if (rc == AROAM_OK) rc = build_impl(*m, st);
+  return finish_model(m, rc, mask, st, out);
+}
+
+int check_grid(const aroam_grid* g) {
+  AROAM_CHECK(g->c_mps > 0 && g->fs_hz > 0 && g->step_m > 0 && g->dz_m > 0, AROAM_EINVAL,
+              "invalid grid spacing");
+  AROAM_CHECK(g->nx >= 1 && g->ny >= 1 && g->nz >= 1 && g->nt >= 1 && g->nx <= 65536 &&
+                  g->ny <= 65536 && g->nz <= 65536 && g->nt <= 65536,
+              AROAM_EINVAL, "grid sizes out of range");
+  AROAM_CHECK(g->k_half >= 0 && g->k_half <= 256, AROAM_EINVAL, "k_half out of range");
+  return AROAM_OK;
+}
+
+int import_model(const aroam_grid* g, const double* dense, const int* col_lo,
+                 const int* col_hi, unsigned mask, hipStream_t st, Model** out) {
+  AROAM_CHECK(g && dense && out, AROAM_EINVAL, "NULL argument to aroam_import_model");
+  *out = nullptr;
+  AROAM_CHECK((col_lo == nullptr) == (col_hi == nullptr), AROAM_EINVAL,
+              "col_lo and col_hi must both be given or both be NULL");
+  AROAM_TRY(check_grid(g));
+  const int K = g->k_half, W = 2 * K + 1, nz = g->nz, nt = g->nt;
+  const size_t ncol = (size_t)W * W * nz;
+  // columns and their windows: as given, or first..last nonzero sample
+  std::vector<int> foi, fk, fsrc, stored, clo, chi, slo;
+  std::vector<long long> soff(1, 0);
+  std::vector<double> values;
+  for (size_t key = 0; key < ncol; ++key) {
+    const double* col = dense + key * nt;
+    int lo = -1, hi = -1;
+    if (col_lo) {
+      lo = col_lo[key];
+      hi = col_hi[key];
+      AROAM_CHECK((lo < 0 && hi < 0) || (0 <= lo && lo <= hi && hi < nt), AROAM_EINVAL,
+                  "column %zu: window [%d, %d] outside [0, %d)", key, lo, hi, nt);
+    } else {
+      for (int n = 0; n < nt; ++n)
+        if (col[n] != 0.0) {
+          if (lo < 0) lo = n;
+          hi = n;
+        }
+    }
+    if (lo < 0) continue;
+    for (int n = lo; n <= hi; ++n)
+      AROAM_CHECK(std::isfinite(col[n]), AROAM_ENONFINITE, "column %zu: non-finite value", key);
+    const int c = (int)clo.size();
+    foi.push_back((int)(key / nz));
+    fk.push_back((int)(key % nz));
+    fsrc.push_back(c);
+    stored.push_back(c);
+    clo.push_back(lo);
+    chi.push_back(hi);
+    slo.push_back(lo);
+    values.insert(values.end(), col + lo, col + hi + 1);
+    soff.push_back((long long)values.size());
+  }
+  Model* m = new (std::nothrow) Model();
+  AROAM_CHECK(m, AROAM_ENOMEM, "host allocation failed");
+  m->grid = *g;
+  m->grid.footprint_mode = 0;
+  m->K = K;
+  m->n_off = W * W;
+  (void)hipGetDevice(&m->device);
+  size_t bytes = 0;
+  int rc = set_columns(*m, foi, fk, fsrc, stored, clo, chi, slo, soff, values, bytes);
+  if (!rc) rc = pack_fp(*m, st, bytes);
+  return finish_model(m, rc, mask, st, out);
+}
+
+// Reduced-precision packs, device-memory accounting, and ownership of a model whose FP64
+// table and FP64 / FP32 packs are built (rc: status of that stage).
+int finish_model(Model* m, int rc, unsigned mask, hipStream_t st, Model** out) {
   if (rc == AROAM_OK) {
     const bool want8 = (mask & ((1u << AROAM_BF16) | (1u << AROAM_FP8E4M3))) != 0;
     size_t bytes = 0;
@@ -730,8 +892,8 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipSt
     return rc;
   }
   // account device memory
-  size_t b = (size_t)std::max<long long>(1, m->nnz) * sizeof(double);
-  b += m->h_colidx.size() * sizeof(int) + m->n_columns * sizeof(int) + m->h_off.size() * 8;
+  size_t b = (size_t)std::max<long long>(1, m->nnz_stored) * sizeof(double);
+  b += m->h_colidx.size() * sizeof(int) + m->n_stored * sizeof(int) + m->h_off.size() * 8;
   for (const Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a})
     b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) + l->h_tile_start.size() * 4 +
          l->n_units * (sizeof(int4) + sizeof(int2));
@@ -743,6 +905,9 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, unsigned mask, hipSt
 
 void destroy_model(Model* m) {
   if (!m) return;
+  (void)hipFree(m->d_fir_taps);
+  (void)hipFree(m->d_fir_pad64);
+  (void)hipFree(m->d_fir_pad32);
   (void)hipFree(m->d_band);
   (void)hipFree(m->d_colidx);
   (void)hipFree(m->d_lo);

@@ -3,6 +3,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -37,12 +38,59 @@ def test_binding_mirrors_every_entry_point():
         assert callable(getattr(P, n)), n
 
 
-def test_struct_layouts_match_header():
-    # field order and C sizes of the public structs
-    assert ctypes.sizeof(P.binding.Sensor) == 48
-    assert ctypes.sizeof(P.binding.Grid) == 64
-    assert ctypes.sizeof(P.binding.SolveOpts) == 56
-    assert ctypes.sizeof(P.binding.SolveInfo) == 48
+_STRUCTS = {"aroam_sensor": "Sensor", "aroam_grid": "Grid", "aroam_model_info": "ModelInfo",
+            "aroam_filter": "Filter",
+            "aroam_solve_opts": "SolveOpts", "aroam_solve_info": "SolveInfo"}
+_RENAMED = {"lambda_": "lambda"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the binding's ctypes structs equal what a C compiler makes of
+    include/aroam.h."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aroam.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS.items():
+        st = getattr(P.binding, pyname)
+        lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{pyname} {f} %zu\\n", offsetof({cname}, {_RENAMED.get(f, f)}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        pyname, field, value = line.split()
+        st = getattr(P.binding, pyname)
+        got = ctypes.sizeof(st) if field == "size" else getattr(st, field).offset
+        assert got == int(value), (pyname, field, got, value)
+
+
+def test_import_model_rejects_bad_tables_without_gpu():
+    """aroam_import_model validates the grid, the windows and the values before any device
+    call."""
+    import numpy as np
+    lib = P.load_library()
+    g = P.binding._grid(dict(c_mps=1500.0, fs_hz=250e6, nx=4, ny=4, step_m=1e-5, nz=3,
+                             dz_m=1e-5, nt=8, k_half=1, footprint_mode=0))
+    H = np.zeros((3, 3, 3, 8))
+    lo = np.full((3, 3, 3), -1, dtype=np.int32)
+    hi = lo.copy()
+    h = ctypes.c_void_p()
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert lib.aroam_import_model(None, ptr(H), None, None, 0, None, ctypes.byref(h)) == -1
+    assert lib.aroam_import_model(ctypes.byref(g), ptr(H), ptr(lo), None, 0, None,
+                                  ctypes.byref(h)) == -1
+    lo[1, 1, 0], hi[1, 1, 0] = 5, 8          # window beyond nt
+    assert lib.aroam_import_model(ctypes.byref(g), ptr(H), ptr(lo), ptr(hi), 0, None,
+                                  ctypes.byref(h)) == -1
+    assert "window" in P.aroam_last_error()
+    H[1, 1, 0, 3] = np.nan                   # non-finite value inside a derived window
+    H[1, 1, 0, 2] = 1.0
+    assert lib.aroam_import_model(ctypes.byref(g), ptr(H), None, None, 0, None,
+                                  ctypes.byref(h)) == -4
+    assert not h.value
 
 
 def test_host_side_argument_errors_without_gpu():
@@ -60,3 +108,20 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(P.binding, "_LIB", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         P.binding.load_library()
+
+
+def test_filtered_build_rejects_bad_filters_without_gpu():
+    import workloads as W
+    lib = P.load_library()
+    cfg = W.config("tiny")
+    sen, g = P.binding._sensor(cfg["sensor"]), P.binding._grid(cfg["grid"])
+    h = ctypes.c_void_p()
+    for f in [(80e6, 0.5e6, 32), (0.5e6, 200e6, 32), (-1.0, 80e6, 32), (0.5e6, 80e6, -1),
+              (0.5e6, 80e6, 128)]:                  # 128 >= nt of the tiny grid
+        filt = P.binding.Filter(*f)
+        assert lib.aroam_build_model_filtered(ctypes.byref(sen), ctypes.byref(g),
+                                              ctypes.byref(filt), 0, None, ctypes.byref(h)) == -1
+        assert not h.value
+    assert lib.aroam_build_model_filtered(ctypes.byref(sen), ctypes.byref(g), None, 0, None,
+                                          ctypes.byref(h)) == -1
+    assert lib.aroam_filter_signals(None, 1, None, None, None) == -1
