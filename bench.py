@@ -52,9 +52,9 @@ def kernel_times(model, dtype, x, s, reps):
     return out
 
 
-def profiled_traffic(dtype, kernel):
+def profiled_traffic(workload, dtype, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the apply kernels have changed since the counters were taken."""
+    when the counters were taken on another workload or the apply kernels have changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "apply_counters.json")
     src = os.path.join(ROOT, "paper_2009_10173_amd", "csrc", "apply.hip")
@@ -63,7 +63,7 @@ def profiled_traffic(dtype, kernel):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if prof.get("apply_hip_sha256") != sha:
+    if prof.get("apply_hip_sha256") != sha or prof.get("workload") != workload:
         return None
     k = prof.get("kernels", {}).get(f"apply {dtype} {kernel}")
     return None if k is None else k["bytes"]
@@ -218,7 +218,7 @@ def main():
                                 else f"{dom} ({args.dtype} MFMA)"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "issued_frac": mfma_issued,
-                     "traffic": profiled_traffic(args.dtype, dom)},
+                     "traffic": profiled_traffic(args.workload, args.dtype, dom)},
     }
     # reduced precision with refinement on the same workload: BF16 (FP8 when the main leg is
     # FP8) applies, FP32 residuals, two sweeps

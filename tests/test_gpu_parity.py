@@ -2,6 +2,7 @@
 seeded inputs.  Tolerances: FP64 <= 1e-12 (relative to the largest entry / L2 norm), FP32
 apply <= 1e-5 relative L2, FP32 reconstruction <= 1e-4 relative L2."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -354,3 +355,31 @@ def test_lsqr_fp8_refined_matches_oracle_schedule(name, sweeps):
     e_ref = rel_l2(x.cpu().numpy(), x_ref)
     print(f"[lsqr fp8 {name}] unrefined {e_plain:.2e} refined ({sweeps} sweeps) {e_ref:.2e}")
     assert e_ref <= 1e-4 and e_ref < e_plain
+
+
+def test_window400_fp8_refined_matches_oracle():
+    """The standalone 64x64 window problem at the 400x400 workload's 5 um step and 81x81-capped
+    cone (depths +-80 um): FP8 (e4m3 table) LSQR, 50 iterations + 2 FP32 residual-correction
+    sweeps, against the FP64 oracle running the same schedule, and plain FP32 LSQR against the
+    oracle's plain LSQR.  The oracle's results are stored by tests/golden/make_window400.py;
+    the signals are recomputed here by the oracle and checked against the stored norm."""
+    from tests.golden.make_window400 import problem
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "window400_lsqr.npz"))
+    cfg, _, _, s = problem()
+    assert abs(np.linalg.norm(s) - float(gold["s_norm"])) <= 1e-12 * float(gold["s_norm"])
+    lam, iters, sweeps = float(gold["lam"]), int(gold["iters"]), int(gold["sweeps"])
+    m = P.Model(cfg["sensor"], cfg["grid"], dtypes=("fp32", "fp8"))
+    try:
+        x8, info = m.solve_lsqr(t32(s), lam=-1.0, iters=iters, inner="fp8", outer="fp32",
+                                refine_sweeps=sweeps)
+        x32, _ = m.solve_lsqr(t32(s), lam=lam, iters=iters, inner="fp32")
+        x8u, _ = m.solve_lsqr(t32(s), lam=lam, iters=iters, inner="fp8")
+        e8 = rel_l2(x8.cpu().numpy(), gold["x_refined"])
+        e8u = rel_l2(x8u.cpu().numpy(), gold["x_plain"])
+        e32 = rel_l2(x32.cpu().numpy(), gold["x_plain"])
+        print(f"[window400] fp8 unrefined {e8u:.2e} fp8 refined {e8:.2e} fp32 {e32:.2e}")
+        assert abs(info["lam"] - lam) <= 1e-5 * lam
+        assert e32 <= 1e-4
+        assert e8 <= 1e-4 and e8 < e8u
+    finally:
+        m.close()
