@@ -101,13 +101,22 @@ def library_path():
 
 
 def load_library():
-    """Load libaroam.so (built by `python -m paper_2009_10173_amd.build`)."""
+    """Load libaroam.so (built by `python -m paper_2009_10173_amd.build`).
+
+    PyTorch's HIP runtime is brought up first, so that the library and the tensors it works
+    on share one runtime in the process (the library's HIP dependency then resolves to the
+    runtime already loaded)."""
     global _LIB
     if _LIB is None:
         path = library_path()
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build the HIP library first "
                                "(python -m paper_2009_10173_amd.build); there is no fallback")
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         lib = C.CDLL(path)
         for name, (args, res) in _SYMBOLS.items():
             fn = getattr(lib, name)
