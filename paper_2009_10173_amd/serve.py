@@ -77,7 +77,7 @@ class ModelCache:
         self.models.clear()
 
 
-def prepare(trace, cache, device="cuda:0"):
+def prepare(trace, cache, device="cuda:0", verbose=False):
     """Inputs of every request: phantom -> FP32 forward -> peak-SNR Gaussian noise (seeded
     GPU generator), plus a result tensor."""
     import torch
@@ -95,11 +95,18 @@ def prepare(trace, cache, device="cuda:0"):
         s = clean + sigma * noise
         reqs.append(dict(req=req, model=model, s=s, x=torch.zeros(model.image_shape,
                                                                    device=device)))
+        _progress(verbose, f"prepared {len(reqs)}/{len(trace)}: side {req['side']}, "
+                           f"nz {req['nz']}, {req['sensor']}, {req['kind']}")
     torch.cuda.synchronize()
     return reqs
 
 
-def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0):
+def _progress(verbose, msg):
+    if verbose:
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+
+def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbose=False):
     """Replay the arrival times through the scheduler; returns per-request records."""
     import torch
     torch.cuda.synchronize()
@@ -125,6 +132,7 @@ def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0):
                 i = by_id[rid]
                 rec[i] = dict(latency=tnow - reqs[i]["req"]["arrival_s"] * time_scale,
                               done_at=tnow, status=info["status"], info=info)
+                _progress(verbose, f"{mode} served {len(rec)}/{len(reqs)} at {tnow:.1f} s")
             if not done and nres == 0 and nq == 0 and nxt < len(order):
                 wait = reqs[order[nxt]]["req"]["arrival_s"] * time_scale - now
                 if wait > 0:
@@ -138,7 +146,7 @@ def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0):
                                                       tick=tick, budget_bytes=budget_bytes))
 
 
-def run_fifo(reqs, mode, time_scale=1.0):
+def run_fifo(reqs, mode, time_scale=1.0, verbose=False):
     """One request at a time in arrival order with the blocking solver entry points."""
     import torch
     torch.cuda.synchronize()
@@ -156,6 +164,7 @@ def run_fifo(reqs, mode, time_scale=1.0):
         info = fn(r["model"].handle, r["s"], r["x"], **o)
         tnow = time.perf_counter() - t0
         rec[i] = dict(latency=tnow - arr, done_at=tnow, status=info["status"], info=info)
+        _progress(verbose, f"{mode} fifo {len(rec)}/{len(reqs)} at {tnow:.1f} s")
     wall = max(r["done_at"] for r in rec.values())
     return _summary(reqs, rec, mode, wall)
 
@@ -184,6 +193,9 @@ def main(argv=None, quiet=False):
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--tick", type=int, default=2)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="arrival rate (requests/s); 0 calibrates it from the FIFO FP32 run")
+    ap.add_argument("--verbose", action="store_true", help="print every completion")
     args = ap.parse_args(argv)
     W = _workloads()
     sides = tuple(int(v) for v in args.sides.split(","))
@@ -192,26 +204,31 @@ def main(argv=None, quiet=False):
     trace = W.serve_trace(args.requests, 1.0, args.seed, sides=sides, nzs=nzs)
     cache = ModelCache()
     t = time.time()
-    reqs = prepare(trace, cache)
+    reqs = prepare(trace, cache, verbose=args.verbose)
     print(f"[serve] prepared {len(reqs)} requests, {len(cache.models)} models in "
           f"{time.time() - t:.1f} s", file=sys.stderr, flush=True)
-    for r in reqs:
-        r["req"]["arrival_s"] = 0.0
-    base0 = run_fifo(reqs, "fp32")
-    service = base0["wall_s"] / len(reqs)
-    rate = args.load / service
+    v = args.verbose
+    if args.rate > 0:
+        rate = args.rate
+        service = args.load / rate
+    else:
+        for r in reqs:
+            r["req"]["arrival_s"] = 0.0
+        base0 = run_fifo(reqs, "fp32", verbose=v)
+        service = base0["wall_s"] / len(reqs)
+        rate = args.load / service
     timed = W.serve_trace(args.requests, rate, args.seed, sides=sides, nzs=nzs)
     for r, tr in zip(reqs, timed):
         r["req"]["arrival_s"] = tr["arrival_s"]
     print(f"[serve] FP32 service time {service:.3f} s/request -> Poisson rate {rate:.2f}/s",
           file=sys.stderr, flush=True)
     res = dict(rate_per_s=rate, fp32_service_s=service)
-    res["fifo_fp32"] = run_fifo(reqs, "fp32")
+    res["fifo_fp32"] = run_fifo(reqs, "fp32", verbose=v)
     print(f"[serve] fifo fp32 done", file=sys.stderr, flush=True)
     budget = int(args.budget_gb * 2 ** 30)
-    res["served_fp32"] = run_served(reqs, "fp32", budget, args.slots, args.tick)
+    res["served_fp32"] = run_served(reqs, "fp32", budget, args.slots, args.tick, verbose=v)
     print(f"[serve] served fp32 done", file=sys.stderr, flush=True)
-    res["served_bf16r"] = run_served(reqs, "bf16r", budget, args.slots, args.tick)
+    res["served_bf16r"] = run_served(reqs, "bf16r", budget, args.slots, args.tick, verbose=v)
     print(f"[serve] served bf16r done", file=sys.stderr, flush=True)
     cache.close()
     torch.cuda.synchronize()
