@@ -25,6 +25,7 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 // Register operands are clang vector types and are reinterpreted with __builtin_bit_cast, so
 // no local variable has its address taken (which would place it in scratch memory).
@@ -137,22 +138,16 @@ __device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
   f.mo = meta[q];
 }
 
-// e4m3 entries of a fragment -> BF16 operand with the K-group's scale applied.
+// e4m3 entries of a fragment -> BF16 operand with the K-group's scale applied.  The scales
+// are powers of two, so the scaled conversion (which applies the exponent of its scale
+// operand) is exact up to the BF16 rounding.
 __device__ __forceinline__ u32x4 decode_fp8(u32x4 v, float sc) {
-  bf16x8 av;
-  const floatx2 f0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, false);
-  const floatx2 f1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, true);
-  const floatx2 f2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.y, false);
-  const floatx2 f3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.y, true);
-  av[0] = (__bf16)(f0.x * sc);
-  av[1] = (__bf16)(f0.y * sc);
-  av[2] = (__bf16)(f1.x * sc);
-  av[3] = (__bf16)(f1.y * sc);
-  av[4] = (__bf16)(f2.x * sc);
-  av[5] = (__bf16)(f2.y * sc);
-  av[6] = (__bf16)(f3.x * sc);
-  av[7] = (__bf16)(f3.y * sc);
-  return __builtin_bit_cast(u32x4, av);
+  const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, sc, false);
+  const bf16x2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, sc, true);
+  const bf16x2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, sc, false);
+  const bf16x2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, sc, true);
+  return u32x4{__builtin_bit_cast(unsigned, p0), __builtin_bit_cast(unsigned, p1),
+               __builtin_bit_cast(unsigned, p2), __builtin_bit_cast(unsigned, p3)};
 }
 
 // Global source and LDS destination of flat stage vector idx of a unit that loads padded
@@ -196,14 +191,18 @@ __device__ __forceinline__ void stage_prefetch(const StagedArgs& a, const T* __r
   }
 }
 
-// MFMAs of one bundle: the NT position fragments are read from LDS, each of the MH table
-// fragments multiplies all of them.
-template <typename T, bool FP8A, int MH, int NT>
-__device__ __forceinline__ void bundle_mfma(const AFrag<T, FP8A, MH>& f, const T* lds,
-                                            const int (&lbase)[NT], floatx4 (&acc)[MH][NT]) {
-  u32x4 xraw[NT];
+// Position fragments of one bundle for the NT tiles of this lane: 16 bytes each from LDS.
+template <typename T, int NT>
+__device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int mo,
+                                       u32x4 (&x)[NT]) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) xraw[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + f.mo);
+  for (int t = 0; t < NT; ++t) x[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + mo);
+}
+
+// MFMAs of one bundle whose position fragments are already in registers.
+template <typename T, bool FP8A, int MH, int NT>
+__device__ __forceinline__ void bundle_mma(const AFrag<T, FP8A, MH>& f, const u32x4 (&xraw)[NT],
+                                           floatx4 (&acc)[MH][NT]) {
 #pragma unroll
   for (int h = 0; h < MH; ++h) {
     u32x4 araw;
@@ -248,7 +247,7 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
   constexpr int RW = BR / 4;
   constexpr int NT = RW * TPR;
   constexpr int PF = 4;                // prefetched stage vectors per thread (>= one row)
-  constexpr int PD = 4;                // table-fragment ring depth
+  constexpr int PD = 4;                // table-fragment ring depth (even)
   constexpr int CH = 4 * VEC;          // chunk = one bundle's four K-groups... per lane group
   const int tile = blockIdx.y;
   const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
@@ -310,14 +309,37 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
         const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
         lbase[t] = (((r + R) % BR) * a.NCOL + c) * a.CS;
       }
-      for (int b0 = U.z; b0 < U.w; b0 += PD) {
+      if constexpr (sizeof(T) == 4) {
+        // FP32: the next bundle's position fragments are read while this bundle's 16 MFMAs
+        // run (two register sets; the FP32 kernel has the registers to spare)
+        u32x4 xa[NT], xb[NT];
+        read_x<T, NT>(lds, lbase, ring[0].mo, xa);
+        for (int b0 = U.z; b0 < U.w; b0 += PD) {
 #pragma unroll
-        for (int j = 0; j < PD; ++j) {
-          if (b0 + j < U.w) bundle_mfma<T, FP8A, MH, NT>(ring[j], lds, lbase, acc);
-          // refill unconditionally (clamped to the unit's last bundle) so that the number of
-          // loads in flight is fixed and the waits can count them
-          load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(b0 + j + PD, U.w - 1), g, n,
-                              ring[j]);
+          for (int j = 0; j < PD; ++j) {
+            // slot (j + 1) mod PD holds the next bundle (or a clamped copy of the last one)
+            read_x<T, NT>(lds, lbase, ring[(j + 1) % PD].mo, (j % 2) ? xa : xb);
+            if (b0 + j < U.w) bundle_mma<T, FP8A, MH, NT>(ring[j], (j % 2) ? xb : xa, acc);
+            // refill unconditionally (clamped to the unit's last bundle) so that the number
+            // of loads in flight is fixed and the waits can count them
+            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(b0 + j + PD, U.w - 1), g, n,
+                                ring[j]);
+          }
+        }
+      } else {
+        // BF16 / FP8: one register set for the position fragments (a second one would cost
+        // the third wave per SIMD, or a shorter table ring, both measured slower)
+        for (int b0 = U.z; b0 < U.w; b0 += PD) {
+#pragma unroll
+          for (int j = 0; j < PD; ++j) {
+            if (b0 + j < U.w) {
+              u32x4 x[NT];
+              read_x<T, NT>(lds, lbase, ring[j].mo, x);
+              bundle_mma<T, FP8A, MH, NT>(ring[j], x, acc);
+            }
+            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(b0 + j + PD, U.w - 1), g, n,
+                                ring[j]);
+          }
         }
       }
     }

@@ -234,7 +234,9 @@ __device__ inline uint8_t f32_to_e4m3(float f) {
   return (uint8_t)(sign | (uint8_t)(eb << 3) | (uint8_t)((int)q - 8));
 }
 
-// Per (offset, 16-depth block) FP32 scale = amax / 448 of the block's table values.
+// Per (offset, 16-depth block) FP32 scale: the smallest power of two >= amax / 448 of the
+// block's table values (powers of two let the kernel apply the scale inside the FP8 -> BF16
+// conversion).
 __global__ void k_block_scale(int n_off, int nz, const int* __restrict__ colidx,
                               const long long* __restrict__ off, const double* __restrict__ band,
                               float* __restrict__ scale) {
@@ -248,7 +250,14 @@ __global__ void k_block_scale(int n_off, int nz, const int* __restrict__ colidx,
     if (c < 0) continue;
     for (long long i = off[c]; i < off[c + 1]; ++i) amax = fmax(amax, fabs(band[i]));
   }
-  scale[id] = amax > 0.0 ? (float)(amax / 448.0) : 1.0f;
+  float sc = 1.0f;
+  if (amax > 0.0) {
+    int e;
+    frexp(amax / 448.0, &e);            // amax / 448 in [2^(e-1), 2^e)
+    sc = ldexpf(1.0f, e);
+    if ((double)ldexpf(1.0f, e - 1) >= amax / 448.0) sc = ldexpf(1.0f, e - 1);
+  }
+  scale[id] = sc;
 }
 
 // FP8 pack: entries are e4m3(value / scale) with the scale of the entry's (offset, 16-depth
