@@ -100,6 +100,7 @@ struct StagedArgs {
   const int4* units;  // (row offset, chunk start, bundle begin, bundle end)
   const int2* urows;  // padded patch rows [lo, hi) each unit loads into the LDS ring
   const int* meta;
+  const int* bmask;   // per bundle: the 16-row halves of the tile its K-groups reach
   int out_len, nx, ny, K, nxp, Lp;
   int ncc;            // patch column chunks
   int NCOL, CS;
@@ -113,12 +114,14 @@ struct AFrag {
   u32x4 v[MH];
   float sc[MH];
   int mo;
+  int hm;  // halves to issue (bit h: half h); uniform over the wave
 };
 
 template <typename T, bool FP8A, int MH>
 __device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
                                        const float* __restrict__ gscale,
-                                       const int* __restrict__ meta, int b, int g, int n,
+                                       const int* __restrict__ meta,
+                                       const int* __restrict__ bmask, int b, int g, int n,
                                        AFrag<T, FP8A, MH>& f) {
   const int q = b * kLaneGroups + g;
 #pragma unroll
@@ -136,6 +139,7 @@ __device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
     }
   }
   f.mo = meta[q];
+  f.hm = MH > 1 ? bmask[b] : 1;
 }
 
 // e4m3 entries of a fragment -> BF16 operand with the K-group's scale applied.  The scales
@@ -205,6 +209,7 @@ __device__ __forceinline__ void bundle_mma(const AFrag<T, FP8A, MH>& f, const u3
                                            floatx4 (&acc)[MH][NT]) {
 #pragma unroll
   for (int h = 0; h < MH; ++h) {
+    if (MH > 1 && !((f.hm >> h) & 1)) continue;  // the bundle's bands miss this half
     u32x4 araw;
     if constexpr (FP8A) araw = decode_fp8(f.v[h], f.sc[h]);
     else araw = f.v[h];
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
       // slot j holds bundle U.z + j (mod PD); the first loads overlap the staging below
 #pragma unroll
       for (int j = 0; j < PD; ++j)
-        load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(U.z + j, U.w - 1), g, n, ring[j]);
+        load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(U.z + j, U.w - 1), g, n, ring[j]);
       __syncthreads();  // every wave is done reading the rows this unit replaces
 #pragma unroll
       for (int i = 0; i < PF; ++i)
@@ -322,7 +327,7 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
             if (b0 + j < U.w) bundle_mma<T, FP8A, MH, NT>(ring[j], (j % 2) ? xb : xa, acc);
             // refill unconditionally (clamped to the unit's last bundle) so that the number
             // of loads in flight is fixed and the waits can count them
-            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(b0 + j + PD, U.w - 1), g, n,
+            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n,
                                 ring[j]);
           }
         }
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
               read_x<T, NT>(lds, lbase, ring[j].mo, x);
               bundle_mma<T, FP8A, MH, NT>(ring[j], x, acc);
             }
-            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, min(b0 + j + PD, U.w - 1), g, n,
+            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n,
                                 ring[j]);
           }
         }
@@ -414,6 +419,7 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out,
   a.units = lay.d_units;
   a.urows = lay.d_ucols;
   a.meta = lay.d_meta;
+  a.bmask = lay.d_bmask;
   a.out_len = lay.out_len;
   a.nx = lay.in.nx;
   a.ny = lay.in.ny;

@@ -79,6 +79,7 @@ struct Layout {
   long long n_bundles = 0;
   int* d_tile_start = nullptr;   // [n_tiles + 1] bundle range of each tile (direct form)
   int* d_meta = nullptr;         // [n_bundles * 4] per K-group offset (see above)
+  int* d_bmask = nullptr;        // staged form: [n_bundles] 16-row halves the bundle reaches
   int4* d_groups = nullptr;      // [n_bundles * 4] (offset index, start, tile, active)
   std::vector<int> h_tile_start;
   long long mac_exec = 0;        // MACs issued per apply

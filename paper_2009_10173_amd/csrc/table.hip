@@ -431,18 +431,20 @@ bool pair_conflict_free(int col_a, int run_a, int col_b, int run_b) {
   return true;
 }
 
-// One K-group of a stage unit: its group record, staged column offset and vector run.
+// One K-group of a stage unit: its group record, staged column offset, vector run, and the
+// 16-row halves of the tile its band reaches (bit h for half h).
 struct UnitEntry {
   int4 group;
   int col, run;
+  int mask;
 };
 
-// Order the K-groups of one stage unit so that bundle slots (0, 1) and (2, 3) read the LDS
+// Pair the K-groups of one stage unit so that bundle slots (0, 1) and (2, 3) read the LDS
 // without bank conflicts wherever possible: a greedy matching over the 64 classes
 // (column mod 16, run) that pairs the most constrained class first.  K-groups left without a
 // partner are paired with each other; an odd one out gets a zero padding K-group of a
-// matching class.  Padding completes the last bundle.  The result has a multiple of four
-// entries.
+// matching class.  The result has an even number of entries; with pad4 it is padded to a
+// multiple of four (whole bundles).
 struct CompatTable {
   std::vector<int> partners[64];  // classes whose K-groups pair with this one without conflicts
   CompatTable() {
@@ -452,7 +454,8 @@ struct CompatTable {
   }
 };
 
-std::vector<UnitEntry> pair_unit(const std::vector<UnitEntry>& in, int maxcol, int t) {
+std::vector<UnitEntry> pair_unit(const std::vector<UnitEntry>& in, int maxcol, int t,
+                                 bool pad4 = true) {
   static const CompatTable table;  // classes (column mod 16, run)
   std::vector<int> cls_items[64];
   for (int i = (int)in.size() - 1; i >= 0; --i)
@@ -490,7 +493,7 @@ std::vector<UnitEntry> pair_unit(const std::vector<UnitEntry>& in, int maxcol, i
     out.push_back(in[ia]);
     out.push_back(in[ib]);
   }
-  const UnitEntry pad0{make_int4(-1, 0, t, 0), 0, 0};
+  const UnitEntry pad0{make_int4(-1, 0, t, 0), 0, 0, 0};
   for (size_t i = 0; i + 1 < left.size(); i += 2) {
     out.push_back(in[left[i]]);
     out.push_back(in[left[i + 1]]);
@@ -509,7 +512,7 @@ std::vector<UnitEntry> pair_unit(const std::vector<UnitEntry>& in, int maxcol, i
     out.push_back(e);
     out.push_back(p);
   }
-  if (out.size() % 4) {
+  if (pad4 && out.size() % 4) {
     UnitEntry p = pad0;
     for (int r = 1; r < 4; ++r)
       if (pair_conflict_free(0, 0, 0, r)) {
@@ -517,6 +520,32 @@ std::vector<UnitEntry> pair_unit(const std::vector<UnitEntry>& in, int maxcol, i
         break;
       }
     out.push_back(pad0);
+    out.push_back(p);
+  }
+  return out;
+}
+
+// Order a stage unit's K-groups into bundles.  With two 16-row halves per tile, K-groups
+// are first grouped by the halves their bands reach, so that most bundles reach only one
+// half and the kernel skips the other half's MFMAs; each group is paired for the LDS as above.
+std::vector<UnitEntry> order_unit(const std::vector<UnitEntry>& in, int maxcol, int t, int NH) {
+  if (NH == 1) return pair_unit(in, maxcol, t);
+  std::vector<UnitEntry> out;
+  for (int mask = 1; mask < (1 << NH); ++mask) {
+    std::vector<UnitEntry> cls;
+    for (const UnitEntry& e : in)
+      if (e.mask == mask) cls.push_back(e);
+    if (cls.empty()) continue;
+    for (const UnitEntry& e : pair_unit(cls, maxcol, t, false)) out.push_back(e);
+  }
+  if (out.size() % 4) {
+    UnitEntry p{make_int4(-1, 0, t, 0), 0, 0, 0};
+    for (int r = 1; r < 4; ++r)
+      if (pair_conflict_free(0, 0, 0, r)) {
+        p.run = r;
+        break;
+      }
+    out.push_back(UnitEntry{make_int4(-1, 0, t, 0), 0, 0, 0});
     out.push_back(p);
   }
   return out;
@@ -548,6 +577,10 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   std::vector<int2> urows;
   std::vector<int> meta, tile_units(lay.n_tiles + 1, 0);
   std::vector<std::vector<char>> hits(W, std::vector<char>((size_t)nq + 1));
+  const int NH = TM / kTile;  // 16-row halves per tile
+  std::vector<std::vector<char>> hhits(NH > 1 ? (size_t)W * NH : 0,
+                                       std::vector<char>((size_t)nq + 1));
+  std::vector<int> bmask;
   std::vector<char> dx_any(W);
   // per (chunk, row-offset slot) list of the current tile's K-groups
   std::vector<std::vector<UnitEntry>> per((size_t)nch * W);
@@ -557,15 +590,25 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
     for (int a = 0; a < W; ++a) {
       // input row offset: +dy for the forward, -dy for the adjoint; slot = offset + K
       const int slot = adjoint ? (W - 1 - a) : a;
-      for (int b = 0; b < W; ++b) dx_any[b] = tile_hits(m, adjoint, G, TM, t, a * W + b, hits[b]);
+      for (int b = 0; b < W; ++b) {
+        dx_any[b] = tile_hits(m, adjoint, G, TM, t, a * W + b, hits[b]);
+        if (NH > 1 && dx_any[b])
+          for (int h = 0; h < NH; ++h)
+            tile_hits(m, adjoint, G, kTile, t * NH + h, a * W + b, hhits[(size_t)b * NH + h]);
+      }
       for (int b = 0; b < W; ++b) {
         if (!dx_any[b]) continue;
         const int col = adjoint ? (W - 1 - b) : b;  // input column offset + K
         for (int q = 0; q < nq; ++q) {
           if (!hits[b][q]) continue;
           const int c = q / qpc;
+          int mask = 1;
+          if (NH > 1) {
+            mask = 0;
+            for (int h = 0; h < NH; ++h) mask |= hhits[(size_t)b * NH + h][q] ? 1 << h : 0;
+          }
           per[(size_t)c * W + slot].push_back(
-              UnitEntry{make_int4(a * W + b, q * G, t, 1), col, (q * G - c * CH) / G});
+              UnitEntry{make_int4(a * W + b, q * G, t, 1), col, (q * G - c * CH) / G, mask});
         }
       }
     }
@@ -575,9 +618,13 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
         auto& lst = per[(size_t)c * W + R];
         if (lst.empty()) continue;
         const size_t first = groups.size();
-        for (const UnitEntry& e : pair_unit(lst, 2 * K, t)) {
+        const std::vector<UnitEntry> ord = order_unit(lst, 2 * K, t, NH);
+        for (size_t i = 0; i < ord.size(); ++i) {
+          const UnitEntry& e = ord[i];
           groups.push_back(e.group);
           meta.push_back(e.col * lay.CS + e.run * G);
+          if (i % kLaneGroups == 0) bmask.push_back(0);
+          bmask.back() |= e.mask;
         }
         const int lo = (prevR < 0 || R >= prevR + BR) ? R : prevR + BR;
         units.push_back(make_int4(R - K, c * CH, (int)(first / kLaneGroups),
@@ -590,13 +637,16 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   tile_units[lay.n_tiles] = (int)units.size();
   lay.n_units = (long long)units.size();
   lay.n_bundles = (long long)groups.size() / kLaneGroups;
-  lay.mac_exec = lay.n_bundles * kLaneGroups * TM * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
+  long long halves = 0;  // 16-row MFMA halves the kernel issues
+  for (int bm : bmask) halves += __builtin_popcount((unsigned)bm);
+  lay.mac_exec = halves * kLaneGroups * kTile * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
   AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
               "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
   AROAM_TRY(alloc_copy(&lay.d_tile_units, tile_units, bytes));
   AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
   AROAM_TRY(alloc_copy(&lay.d_ucols, urows, bytes));
   AROAM_TRY(alloc_copy(&lay.d_meta, meta, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_bmask, bmask, bytes));
   AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
   lay.h_tile_start = tile_units;
   return AROAM_OK;
@@ -1022,6 +1072,7 @@ int finish_model(Model* m, int rc, unsigned mask, hipStream_t st, Model** out) {
   b += m->h_colidx.size() * sizeof(int) + m->n_stored * sizeof(int) + m->h_off.size() * 8;
   for (const Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a})
     b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) + l->h_tile_start.size() * 4 +
+         (l->staged ? l->n_bundles * sizeof(int) : 0) +
          l->n_units * (sizeof(int4) + sizeof(int2));
   for (int d = 0; d < 4; ++d) b += m->fwd_pack[d].bytes + m->adj_pack[d].bytes;
   m->device_bytes = b;
@@ -1041,6 +1092,7 @@ void destroy_model(Model* m) {
   for (Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a}) {
     (void)hipFree(l->d_tile_start);
     (void)hipFree(l->d_meta);
+    (void)hipFree(l->d_bmask);
     (void)hipFree(l->d_groups);
     (void)hipFree(l->d_tile_units);
     (void)hipFree(l->d_units);
