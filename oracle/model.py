@@ -136,46 +136,112 @@ def footprint(sensor, grid):
 # ---------------------------------------------------------------------------------------
 # The compressed model: columns for one scan position (Methods, scanning symmetries).
 
-def column(sensor, grid, elems, dx, dy, k):
-    """Time signal of voxel (dx, dy, k) relative to the scan position, length Nt (FP64).
+def discretisation(grid):
+    """(voxel basis, time derivative, quadrature points per half axis) of a grid.
 
-    Direct sum over sub-elements (Eq. 3-4) of dS_j/(2 pi r_j) e'(tau_nj)."""
-    pos, area = elems
-    sigma, omega = eir_params(sensor, grid)
+    Voxel basis 0: a point absorber at the voxel centre; 1: the trilinear (tent) basis of
+    the paper's discretisation (Methods, Forward modeling: trilinear interpolation of
+    neighbouring voxel values).  Time derivative 0: the analytic derivative of the EIR;
+    1: the central finite difference of the paper's discretisation, applied to the
+    band-limited signal (the truncated EIR)."""
+    return (int(grid.get("voxel_basis", 0)), int(grid.get("time_derivative", 0)),
+            int(grid.get("basis_quad", 3)))
+
+
+def tent_rule(q):
+    """Nodes and weights on [-1, 1] for integrals of f(t) (1 - |t|): q-point Gauss-Legendre
+    on each half [-1, 0] and [0, 1] with the tent factor folded into the weights (exact when
+    f (1 - |t|) is a polynomial of degree <= 2q - 1 on each half)."""
+    x, w = np.polynomial.legendre.leggauss(q)            # on [-1, 1]
+    t = 0.5 * (x + 1.0)                                   # on [0, 1]
+    wt = 0.5 * w * (1.0 - t)
+    return np.concatenate([-t[::-1], t]), np.concatenate([wt[::-1], wt])
+
+
+def basis_points(grid):
+    """Quadrature of the voxel basis: offsets (mm) from the voxel centre and weights.
+
+    The trilinear basis is the product of tents 1 - |t| (t in voxel spacings, |t| <= 1) along
+    x, y and z; each axis uses `tent_rule`, whose weights sum to one."""
+    vb, _, Q = discretisation(grid)
+    if vb == 0:
+        return np.zeros((1, 3)), np.ones(1)
+    t, w = tent_rule(Q)
+    step, dz = grid["step_m"] * MM, grid["dz_m"] * MM
+    X, Y, Z = np.meshgrid(t * step, t * step, t * dz, indexing="ij")
+    WX, WY, WZ = np.meshgrid(w, w, w, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1), (WX * WY * WZ).ravel()
+
+
+def derivative_kernel(tau, sigma, omega, deriv):
+    """Time derivative of the electrical response truncated at 5 sigma, in samples:
+    analytic e'(tau), or the central difference (e(tau + 1) - e(tau - 1)) / 2."""
+    cut = EIR_CUTOFF_SIGMAS * sigma
+    tau = np.asarray(tau, dtype=np.float64)
+    if deriv == 0:
+        v = eir_derivative(tau, sigma, omega)
+        v[np.abs(tau) > cut] = 0.0
+        return v
+    ep = eir(tau + 1.0, sigma, omega)
+    ep[np.abs(tau + 1.0) > cut] = 0.0
+    em = eir(tau - 1.0, sigma, omega)
+    em[np.abs(tau - 1.0) > cut] = 0.0
+    return 0.5 * (ep - em)
+
+
+def _kernel_reach(sigma, deriv):
+    return EIR_CUTOFF_SIGMAS * sigma + (1.0 if deriv else 0.0)
+
+
+def _delays(sensor, grid, elems, dx, dy, k):
+    """Distances r (mm) and delays (samples) of every (basis point, sub-element) pair."""
+    pos, _ = elems
     R = sensor["radius_m"] * MM
     c_over_fs = grid["c_mps"] * MM / grid["fs_hz"]          # mm per sample
     step = grid["step_m"] * MM
     p = np.array([dx * step, dy * step, depths_mm(grid)[k]])
-    r = np.sqrt(np.sum((p[None, :] - pos) ** 2, axis=1))   # [M]
-    delay = (r - R) / c_over_fs                               # samples
-    # Only samples within 5 sigma of some sub-element's arrival can be nonzero.
+    offs, wq = basis_points(grid)
+    pts = p[None, :] + offs                                   # [Q, 3]
+    r = np.sqrt(np.sum((pts[:, None, :] - pos[None, :, :]) ** 2, axis=2))   # [Q, M]
+    return r, (r - R) / c_over_fs, wq
+
+
+def column(sensor, grid, elems, dx, dy, k):
+    """Time signal of voxel (dx, dy, k) relative to the scan position, length Nt (FP64).
+
+    Direct sum over sub-elements (Eq. 3-4) of dS_j/(2 pi r_j) e'(tau_nj); for the trilinear
+    basis, the weighted sum of that over the basis quadrature points."""
+    _, area = elems
+    sigma, omega = eir_params(sensor, grid)
+    _, deriv, _ = discretisation(grid)
+    r, delay, wq = _delays(sensor, grid, elems, dx, dy, k)
+    # Only samples within the kernel's reach of some arrival can be nonzero.
     nt = grid["nt"]
-    lo = max(0, math.ceil(nt // 2 + delay.min() - EIR_CUTOFF_SIGMAS * sigma))
-    hi = min(nt - 1, math.floor(nt // 2 + delay.max() + EIR_CUTOFF_SIGMAS * sigma))
+    reach = _kernel_reach(sigma, deriv)
+    lo = max(0, math.ceil(nt // 2 + delay.min() - reach))
+    hi = min(nt - 1, math.floor(nt // 2 + delay.max() + reach))
     out = np.zeros(nt)
     if lo > hi:
         return out
     n = np.arange(lo, hi + 1, dtype=np.float64)
-    tau = (n[:, None] - nt // 2) - delay[None, :]            # [samples, M]
-    w = area / (2.0 * math.pi * r)
-    term = eir_derivative(tau, sigma, omega) * w[None, :]
-    term[np.abs(tau) > EIR_CUTOFF_SIGMAS * sigma] = 0.0
-    out[lo:hi + 1] = term.sum(axis=1)
+    acc = np.zeros(hi - lo + 1)
+    for q in range(len(wq)):
+        tau = (n[:, None] - nt // 2) - delay[q][None, :]     # [samples, M]
+        w = area / (2.0 * math.pi * r[q])
+        term = derivative_kernel(tau, sigma, omega, deriv) * w[None, :]
+        acc += wq[q] * term.sum(axis=1)
+    out[lo:hi + 1] = acc
     return out
 
 
 def column_support(sensor, grid, elems, dx, dy, k):
     """Inclusive sample range [n_lo, n_hi] outside which the column is exactly zero."""
-    pos, _ = elems
     sigma, _ = eir_params(sensor, grid)
-    R = sensor["radius_m"] * MM
-    c_over_fs = grid["c_mps"] * MM / grid["fs_hz"]
-    step = grid["step_m"] * MM
-    p = np.array([dx * step, dy * step, depths_mm(grid)[k]])
-    r = np.sqrt(np.sum((p[None, :] - pos) ** 2, axis=1))
-    delay = (r - R) / c_over_fs
-    lo = math.ceil(grid["nt"] // 2 + delay.min() - EIR_CUTOFF_SIGMAS * sigma)
-    hi = math.floor(grid["nt"] // 2 + delay.max() + EIR_CUTOFF_SIGMAS * sigma)
+    _, deriv, _ = discretisation(grid)
+    _, delay, _ = _delays(sensor, grid, elems, dx, dy, k)
+    reach = _kernel_reach(sigma, deriv)
+    lo = math.ceil(grid["nt"] // 2 + delay.min() - reach)
+    hi = math.floor(grid["nt"] // 2 + delay.max() + reach)
     return max(lo, 0), min(hi, grid["nt"] - 1)
 
 
