@@ -16,6 +16,11 @@ Reading of the paper used here (each choice is also listed in the design notes):
   z_k = (k - Nz/2) dz from the focal plane, positive = away from the sensor.
 * The EIR is a zero-phase Gaussian-modulated cosine with centre f0 and an amplitude
   -6 dB bandwidth of frac_bw * f0; a term enters the sum iff |tau| <= 5 sigma.
+* The paper's own discretisation (Methods, Forward modeling: finite differences in time,
+  trilinear interpolation of voxel values on the integration sphere) is available as an
+  option: a trilinear (tent) voxel basis, integrated by a Gauss rule over each voxel, and a
+  central difference of the band-limited signal instead of the analytic derivative.  The
+  default is the point voxel with the analytic derivative.
 * Lateral cut-off (Results, first paragraph; Methods, scanning symmetries: the model is
   set to zero where the sensitivity drops): offsets |dx|,|dy| <= K, and in mode 1 also
   the cone (dx^2+dy^2) step^2 <= (rho0 + |z| tan(theta_m))^2 with rho0 = 2 * 0.71 lambda/NA
