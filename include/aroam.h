@@ -68,7 +68,16 @@ typedef struct {
  *   k_half         lateral model extent: offsets -k_half..k_half in x and y
  *   footprint_mode 0: full (2 k_half + 1)^2 square at every depth;
  *                  1: also (dx^2 + dy^2) step^2 <= (rho0 + |z| tan(theta_max))^2 with
- *                     rho0 = 2 * 0.71 lambda(f0) / NA (the diffraction-limit rule, Results)  */
+ *                     rho0 = 2 * 0.71 lambda(f0) / NA (the diffraction-limit rule, Results)
+ * Discretisation of the model (Methods, Forward modeling); zero-initialised fields select the
+ * point voxel with the analytic derivative:
+ *   voxel_basis     0: point absorber at the voxel centre; 1: trilinear (tent) basis of half
+ *                   width one voxel spacing in x, y and z, integrated over the voxel by the
+ *                   product of basis_quad-point Gauss-Legendre rules on each half axis with
+ *                   the tent folded into the weights
+ *   time_derivative 0: analytic derivative of the EIR; 1: central difference
+ *                   (s(n + 1) - s(n - 1)) / 2 of the band-limited signal
+ *   basis_quad      Gauss points per half axis of the trilinear basis, 1..8 (0 = 3)        */
 typedef struct {
   double c_mps, fs_hz;
   int nx, ny;
@@ -78,6 +87,9 @@ typedef struct {
   int nt;
   int k_half;
   int footprint_mode;
+  int voxel_basis;
+  int time_derivative;
+  int basis_quad;
 } aroam_grid;
 
 /* Sizes and work figures of a built model. */

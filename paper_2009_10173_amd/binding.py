@@ -32,7 +32,8 @@ class Sensor(C.Structure):
 class Grid(C.Structure):
     _fields_ = [("c_mps", C.c_double), ("fs_hz", C.c_double), ("nx", C.c_int), ("ny", C.c_int),
                 ("step_m", C.c_double), ("nz", C.c_int), ("dz_m", C.c_double), ("nt", C.c_int),
-                ("k_half", C.c_int), ("footprint_mode", C.c_int)]
+                ("k_half", C.c_int), ("footprint_mode", C.c_int), ("voxel_basis", C.c_int),
+                ("time_derivative", C.c_int), ("basis_quad", C.c_int)]
 
 
 class Filter(C.Structure):
@@ -151,7 +152,8 @@ def _sensor(d):
 
 def _grid(d):
     return Grid(d["c_mps"], d["fs_hz"], d["nx"], d["ny"], d["step_m"], d["nz"], d["dz_m"],
-                d["nt"], d["k_half"], d["footprint_mode"])
+                d["nt"], d["k_half"], d["footprint_mode"], int(d.get("voxel_basis", 0)),
+                int(d.get("time_derivative", 0)), int(d.get("basis_quad", 0)))
 
 
 # --- one function per C entry point ---------------------------------------------------------

@@ -70,7 +70,29 @@ struct Geo {
   double step, R, cfs, sigma5, inv2s2, invs2, omega;
   int nz, nt, M;
   double dz_m;
+  double reach;      // samples around an arrival that the derivative kernel can touch
+  int fd;            // 0: analytic derivative of the EIR, 1: central difference
+  int nq;            // basis quadrature points (1 for the point voxel)
 };
+
+// Time derivative of the EIR truncated at 5 sigma (samples): the analytic e'(tau), or the
+// central difference (e(tau + 1) - e(tau - 1)) / 2 (Methods, Forward modeling: finite
+// differences in time).
+__device__ inline double eir_trunc(double tau, const Geo& geo) {
+  if (fabs(tau) > geo.sigma5) return 0.0;
+  double sn, cs;
+  sincos(geo.omega * tau, &sn, &cs);
+  return exp(-tau * tau * geo.inv2s2) * cs;
+}
+
+__device__ inline double deriv_kernel(double tau, const Geo& geo) {
+  if (geo.fd) return 0.5 * (eir_trunc(tau + 1.0, geo) - eir_trunc(tau - 1.0, geo));
+  if (fabs(tau) > geo.sigma5) return 0.0;
+  const double g = exp(-tau * tau * geo.inv2s2);
+  double sn, cs;
+  sincos(geo.omega * tau, &sn, &cs);
+  return -g * ((tau * geo.invs2) * cs + geo.omega * sn);
+}
 
 // Distance-derived quantities of sub-element j for the voxel p (mm): the path difference
 // r - R is formed as (r^2 - R^2) / (r + R) with r^2 - R^2 = |p|^2 - 2 p.e + (|e|^2 - R^2), so
@@ -82,35 +104,40 @@ __device__ inline void path(double px, double py, double pz, double p2, double e
   dr = q / (r + R);
 }
 
+// Window of every column: the samples within the kernel's reach of some arrival, over all
+// sub-elements and basis quadrature points (qp: offsets in mm, x y z per point).
 __global__ void k_support(int n, const int* __restrict__ cdx, const int* __restrict__ cdy,
                           const int* __restrict__ ck, const double* __restrict__ ex,
                           const double* __restrict__ ey, const double* __restrict__ ez,
-                          const double* __restrict__ eoff, Geo geo, int* __restrict__ lo,
-                          int* __restrict__ hi) {
+                          const double* __restrict__ eoff, const double* __restrict__ qp,
+                          Geo geo, int* __restrict__ lo, int* __restrict__ hi) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  const double px = cdx[c] * geo.step, py = cdy[c] * geo.step;
-  const double pz = ((ck[c] - geo.nz / 2) * geo.dz_m) * 1e3;
-  const double p2 = px * px + py * py + pz * pz;
   double dmin = 1e300, dmax = -1e300;
-  for (int j = 0; j < geo.M; ++j) {
-    double r, dr;
-    path(px, py, pz, p2, ex[j], ey[j], ez[j], eoff[j], geo.R, r, dr);
-    const double d = dr / geo.cfs;
-    dmin = fmin(dmin, d);
-    dmax = fmax(dmax, d);
+  for (int q = 0; q < geo.nq; ++q) {
+    const double px = cdx[c] * geo.step + qp[3 * q], py = cdy[c] * geo.step + qp[3 * q + 1];
+    const double pz = ((ck[c] - geo.nz / 2) * geo.dz_m) * 1e3 + qp[3 * q + 2];
+    const double p2 = px * px + py * py + pz * pz;
+    for (int j = 0; j < geo.M; ++j) {
+      double r, dr;
+      path(px, py, pz, p2, ex[j], ey[j], ez[j], eoff[j], geo.R, r, dr);
+      const double d = dr / geo.cfs;
+      dmin = fmin(dmin, d);
+      dmax = fmax(dmax, d);
+    }
   }
   const int h = geo.nt / 2;
-  int a = (int)ceil(h + dmin - geo.sigma5);
-  int b = (int)floor(h + dmax + geo.sigma5);
+  int a = (int)ceil(h + dmin - geo.reach);
+  int b = (int)floor(h + dmax + geo.reach);
   a = max(a, 0);
   b = min(b, geo.nt - 1);
   lo[c] = a <= b ? a : -1;
   hi[c] = a <= b ? b : -1;
 }
 
-// One wave per active column: the wave first tabulates every sub-element's delay and
-// weight in LDS, then each lane sums the sub-elements for its time samples in FP64.
+// One wave per stored column: for every basis quadrature point (qw: weights) the wave
+// tabulates each sub-element's delay and weight in LDS, then each lane adds the
+// sub-elements' terms for its time samples in FP64.
 __global__ __launch_bounds__(64) void k_table(const int* __restrict__ cdx,
                                              const int* __restrict__ cdy,
                                              const int* __restrict__ ck,
@@ -120,37 +147,38 @@ __global__ __launch_bounds__(64) void k_table(const int* __restrict__ cdx,
                                              const double* __restrict__ ey,
                                              const double* __restrict__ ez,
                                              const double* __restrict__ eoff,
-                                             const double* __restrict__ area, Geo geo,
+                                             const double* __restrict__ area,
+                                             const double* __restrict__ qp,
+                                             const double* __restrict__ qw, Geo geo,
                                              double* __restrict__ band) {
   extern __shared__ double sh[];  // [M] delay (samples), [M] weight dS / (2 pi r)
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
-  const double px = cdx[c] * geo.step, py = cdy[c] * geo.step;
-  const double pz = ((ck[c] - geo.nz / 2) * geo.dz_m) * 1e3;
-  const double p2 = px * px + py * py + pz * pz;
-  for (int j = lane; j < geo.M; j += 64) {
-    double r, dr;
-    path(px, py, pz, p2, ex[j], ey[j], ez[j], eoff[j], geo.R, r, dr);
-    sh[j] = dr / geo.cfs;
-    sh[geo.M + j] = area[j] / (2.0 * kPi * r);
-  }
-  __syncthreads();
   const int l = lo[c];
   const long long o = off[c];
   const int len = (int)(off[c + 1] - o);
-  for (int i = lane; i < len; i += 64) {
-    const double nrel = (double)(l + i - geo.nt / 2);
-    double acc = 0.0;
-    for (int j = 0; j < geo.M; ++j) {
-      const double tau = nrel - sh[j];
-      if (fabs(tau) <= geo.sigma5) {
-        const double g = exp(-tau * tau * geo.inv2s2);
-        double sn, cs;
-        sincos(geo.omega * tau, &sn, &cs);
-        acc += sh[geo.M + j] * (-g * ((tau * geo.invs2) * cs + geo.omega * sn));
-      }
+  for (int i = lane; i < len; i += 64) band[o + i] = 0.0;
+  for (int q = 0; q < geo.nq; ++q) {
+    const double px = cdx[c] * geo.step + qp[3 * q], py = cdy[c] * geo.step + qp[3 * q + 1];
+    const double pz = ((ck[c] - geo.nz / 2) * geo.dz_m) * 1e3 + qp[3 * q + 2];
+    const double p2 = px * px + py * py + pz * pz;
+    __syncthreads();  // the previous point's table is no longer read
+    for (int j = lane; j < geo.M; j += 64) {
+      double r, dr;
+      path(px, py, pz, p2, ex[j], ey[j], ez[j], eoff[j], geo.R, r, dr);
+      sh[j] = dr / geo.cfs;
+      sh[geo.M + j] = area[j] / (2.0 * kPi * r);
     }
-    band[o + i] = acc;
+    __syncthreads();
+    for (int i = lane; i < len; i += 64) {
+      const double nrel = (double)(l + i - geo.nt / 2);
+      double acc = 0.0;
+      for (int j = 0; j < geo.M; ++j) {
+        const double tau = nrel - sh[j];
+        if (fabs(tau) <= geo.reach) acc += sh[geo.M + j] * deriv_kernel(tau, geo);
+      }
+      band[o + i] += qw[q] * acc;
+    }
   }
 }
 
@@ -712,6 +740,75 @@ int set_columns(Model& m, const std::vector<int>& foi, const std::vector<int>& f
                 const std::vector<double>& values, size_t& bytes);
 int pack_fp(Model& m, hipStream_t st, size_t& bytes);
 
+// q-point Gauss-Legendre nodes and weights on [-1, 1]: roots of the Legendre polynomial P_q
+// by Newton's method from the usual cosine guesses, weights 2 / ((1 - x^2) P_q'(x)^2).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (q + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q == 1 ? 1.0 : q * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= q; ++k) {
+      const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = q == 1 ? 1.0 : q * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Quadrature of the voxel basis (Methods, Forward modeling: trilinear interpolation of
+// neighbouring voxel values): offsets (mm, x y z per point) and weights.  The point voxel is
+// one point at the centre.  The trilinear basis is the product of tents 1 - |t| along x, y
+// and z (t in voxel spacings); each axis takes q Gauss-Legendre points on each half with the
+// tent folded into the weights, which sum to one.
+void basis_points(const aroam_grid& g, std::vector<double>& qp, std::vector<double>& qw) {
+  qp.clear();
+  qw.clear();
+  if (g.voxel_basis == 0) {
+    qp = {0.0, 0.0, 0.0};
+    qw = {1.0};
+    return;
+  }
+  const int q = g.basis_quad > 0 ? g.basis_quad : 3;
+  std::vector<double> x, w, t, wt;
+  gauss_legendre(q, x, w);
+  // nodes t on [0, 1] in ascending order with weights w/2 (1 - t)
+  std::vector<std::pair<double, double>> half(q);
+  for (int i = 0; i < q; ++i) {
+    const double th = 0.5 * (x[i] + 1.0);
+    half[i] = {th, 0.5 * w[i] * (1.0 - th)};
+  }
+  std::sort(half.begin(), half.end());
+  std::vector<double> th(q), wh(q);
+  for (int i = 0; i < q; ++i) th[i] = half[i].first, wh[i] = half[i].second;
+  for (int i = q - 1; i >= 0; --i) t.push_back(-th[i]), wt.push_back(wh[i]);
+  for (int i = 0; i < q; ++i) t.push_back(th[i]), wt.push_back(wh[i]);
+  const double step = g.step_m * kMM, dz = g.dz_m * kMM;
+  for (size_t a = 0; a < t.size(); ++a)
+    for (size_t b = 0; b < t.size(); ++b)
+      for (size_t c = 0; c < t.size(); ++c) {
+        qp.push_back(t[a] * step);
+        qp.push_back(t[b] * step);
+        qp.push_back(t[c] * dz);
+        qw.push_back(wt[a] * wt[b] * wt[c]);
+      }
+}
+
 int build_impl(Model& m, hipStream_t st) {
   const aroam_sensor& s = m.sensor;
   const aroam_grid& g = m.grid;
@@ -774,16 +871,25 @@ int build_impl(Model& m, hipStream_t st) {
   geo.nt = g.nt;
   geo.M = m.M;
   geo.dz_m = g.dz_m;
+  geo.fd = g.time_derivative;
+  geo.reach = geo.sigma5 + (g.time_derivative ? 1.0 : 0.0);
+  std::vector<double> qp, qw;
+  basis_points(g, qp, qw);
+  geo.nq = (int)qw.size();
 
   double *d_ex = nullptr, *d_ey = nullptr, *d_ez = nullptr, *d_eoff = nullptr, *d_area = nullptr;
   int *d_cdx = nullptr, *d_cdy = nullptr, *d_ck = nullptr, *d_clo = nullptr, *d_chi = nullptr;
+  double *d_qp = nullptr, *d_qw = nullptr;
   size_t tmp = 0;
   int rc = AROAM_OK;
   auto cleanup = [&]() {
     (void)hipFree(d_ex); (void)hipFree(d_ey); (void)hipFree(d_ez); (void)hipFree(d_eoff); (void)hipFree(d_area);
     (void)hipFree(d_cdx); (void)hipFree(d_cdy); (void)hipFree(d_ck); (void)hipFree(d_clo); (void)hipFree(d_chi);
+    (void)hipFree(d_qp); (void)hipFree(d_qw);
   };
   do {
+    if ((rc = alloc_copy(&d_qp, qp, tmp))) break;
+    if ((rc = alloc_copy(&d_qw, qw, tmp))) break;
     if ((rc = alloc_copy(&d_ex, ex, tmp))) break;
     if ((rc = alloc_copy(&d_ey, ey, tmp))) break;
     if ((rc = alloc_copy(&d_ez, ez, tmp))) break;
@@ -797,7 +903,7 @@ int build_impl(Model& m, hipStream_t st) {
     if ((rc = alloc_copy(&d_chi, zeros, tmp))) break;
     if (nc > 0) {
       hipLaunchKernelGGL(k_support, dim3((unsigned)ceil_div(nc, 128)), dim3(128), 0, st, nc,
-                         d_cdx, d_cdy, d_ck, d_ex, d_ey, d_ez, d_eoff, geo, d_clo, d_chi);
+                         d_cdx, d_cdy, d_ck, d_ex, d_ey, d_ez, d_eoff, d_qp, geo, d_clo, d_chi);
       if (hipGetLastError() != hipSuccess) { set_error("support kernel launch failed"); rc = AROAM_EDEVICE; break; }
     }
     std::vector<int> clo(nc), chi(nc);
@@ -863,8 +969,8 @@ int build_impl(Model& m, hipStream_t st) {
     if (m.n_stored > 0) {
       hipLaunchKernelGGL(k_table, dim3((unsigned)m.n_stored), dim3(64), 2 * m.M * sizeof(double),
                          st, d_sdx, d_sdy, d_sk, m.filtered ? d_rlo : m.d_lo,
-                         m.filtered ? d_roff : m.d_off, d_ex, d_ey, d_ez, d_eoff, d_area, geo,
-                         m.filtered ? d_raw : m.d_band);
+                         m.filtered ? d_roff : m.d_off, d_ex, d_ey, d_ez, d_eoff, d_area, d_qp,
+                         d_qw, geo, m.filtered ? d_raw : m.d_band);
       if (hipGetLastError() != hipSuccess) { set_error("table kernel launch failed"); rc = AROAM_EDEVICE; }
       if (rc == AROAM_OK && m.filtered) rc = filter_columns(m, d_rlo, d_roff, d_raw, st);
     }
@@ -958,6 +1064,10 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, const aroam_filter* 
   AROAM_CHECK(g->footprint_mode == 0 || g->footprint_mode == 1, AROAM_EINVAL,
               "footprint_mode must be 0 or 1");
   if (f) AROAM_TRY(check_filter(*f, g->fs_hz, g->nt));
+  AROAM_CHECK((g->voxel_basis == 0 || g->voxel_basis == 1) &&
+                  (g->time_derivative == 0 || g->time_derivative == 1) && g->basis_quad >= 0 &&
+                  g->basis_quad <= 8,
+              AROAM_EINVAL, "voxel_basis, time_derivative must be 0 or 1, basis_quad 0..8");
   Model* m = new (std::nothrow) Model();
   AROAM_CHECK(m, AROAM_ENOMEM, "host allocation failed");
   m->sensor = *s;

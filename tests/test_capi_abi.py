@@ -125,3 +125,16 @@ def test_filtered_build_rejects_bad_filters_without_gpu():
     assert lib.aroam_build_model_filtered(ctypes.byref(sen), ctypes.byref(g), None, 0, None,
                                           ctypes.byref(h)) == -1
     assert lib.aroam_filter_signals(None, 1, None, None, None) == -1
+
+
+def test_build_rejects_bad_discretisation_without_gpu():
+    import workloads as W
+    lib = P.load_library()
+    cfg = W.config("tiny")
+    sen = P.binding._sensor(cfg["sensor"])
+    h = ctypes.c_void_p()
+    for bad in (dict(voxel_basis=2), dict(time_derivative=-1), dict(basis_quad=9)):
+        g = P.binding._grid(dict(cfg["grid"], **bad))
+        assert lib.aroam_build_model(ctypes.byref(sen), ctypes.byref(g), 0, None,
+                                     ctypes.byref(h)) == -1
+        assert not h.value
