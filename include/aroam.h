@@ -106,6 +106,12 @@ typedef struct {
                              * per symmetry class of the square (H[dx,dy] = H[+-dx,+-dy] =
                              * H[dy,dx]), an imported one every column it was given */
   long long stored_nnz;  /* FP64 band entries held on the device                                   */
+  int row_tiles[4];      /* output row tiles of the forward kernel (time samples), by aroam_dtype  */
+  int row_tiles_adj[4];  /* the same for the adjoint (depths)                                      */
+  int pieces[4];         /* workgroup rows of the forward launch: row_tiles, or more where the
+                          * stage units of heavy tiles are cut into pieces whose partial sums a
+                          * second kernel adds (load balance of the launch)                       */
+  int pieces_adj[4];     /* the same for the adjoint                                               */
 } aroam_model_info;
 
 /* Build the compressed model (Methods, "Efficient reconstruction based on scanning

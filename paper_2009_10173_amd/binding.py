@@ -45,7 +45,9 @@ class ModelInfo(C.Structure):
                 ("mac_exec", C.c_longlong * 4), ("mac_exec_adj", C.c_longlong * 4),
                 ("device_bytes", C.c_size_t), ("n_elements", C.c_int),
                 ("dtype_mask", C.c_uint), ("stored_columns", C.c_longlong),
-                ("stored_nnz", C.c_longlong)]
+                ("stored_nnz", C.c_longlong), ("row_tiles", C.c_int * 4),
+                ("row_tiles_adj", C.c_int * 4), ("pieces", C.c_int * 4),
+                ("pieces_adj", C.c_int * 4)]
 
 
 class SolveOpts(C.Structure):
@@ -217,7 +219,9 @@ def aroam_model_query(h):
                 mac_exec=list(info.mac_exec), mac_exec_adj=list(info.mac_exec_adj),
                 device_bytes=info.device_bytes, n_elements=info.n_elements,
                 dtype_mask=info.dtype_mask, stored_columns=info.stored_columns,
-                stored_nnz=info.stored_nnz)
+                stored_nnz=info.stored_nnz, row_tiles=list(info.row_tiles),
+                row_tiles_adj=list(info.row_tiles_adj), pieces=list(info.pieces),
+                pieces_adj=list(info.pieces_adj))
 
 
 def aroam_model_export_table(h, grid, dense=True):

@@ -96,7 +96,10 @@ __global__ __launch_bounds__(256) void k_apply_fma(const T* __restrict__ pack, c
 }
 
 struct StagedArgs {
-  const int* tile_units;
+  const int4* pieces;      // (tile, unit begin, unit end, partial slot or -1)
+  const int2* tile_split;  // per tile: (pieces, first slot)
+  float* partial;          // [slot][patch][position][TM rows] partial sums of cut tiles
+  int n_patches;
   const int4* units;  // (row offset, chunk start, bundle begin, bundle end)
   const int2* urows;  // padded patch rows [lo, hi) each unit loads into the LDS ring
   const int* meta;
@@ -254,7 +257,8 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
   constexpr int PF = 4;                // prefetched stage vectors per thread (>= one row)
   constexpr int PD = 4;                // table-fragment ring depth (even)
   constexpr int CH = 4 * VEC;          // chunk = one bundle's four K-groups... per lane group
-  const int tile = blockIdx.y;
+  const int4 piece = a.pieces[blockIdx.y];
+  const int tile = piece.x;
   const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int n = lane % 16, g = lane / 16;
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
   for (int h = 0; h < MH; ++h)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[h][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int u0 = a.tile_units[tile], u1 = a.tile_units[tile + 1];
+  const int u0 = piece.y, u1 = piece.z;
   if (u0 < u1) {
     u32x4 pf[PF];
     int pf_off[PF];
@@ -349,17 +353,62 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
       }
     }
   }
+  // the output, or for a piece of a cut tile its partial slot (the patch's positions in order,
+  // TM rows each), which k_add_slots adds up
+  constexpr int PS = BR * BC * 16 * MH;  // floats per slot and patch
+  float* slot =
+      piece.w >= 0 ? a.partial + ((long long)piece.w * a.n_patches + blockIdx.x) * PS : nullptr;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int py = py0 + wave * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
     if (py >= a.ny || px >= a.nx) continue;
-    float* o = out + ((long long)py * a.nx + px) * a.out_len;
+    const int local = (wave * RW + t / TPR) * BC + (t % TPR) * 16 + n;
+    float* o = slot ? slot + (long long)local * (16 * MH) - 16 * MH * tile
+                    : out + ((long long)py * a.nx + px) * a.out_len;
 #pragma unroll
     for (int h = 0; h < MH; ++h)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = 16 * MH * tile + 16 * h + 4 * g + i;
         if (row < a.out_len) o[row] = acc[h][t][i];
+      }
+  }
+}
+
+// Output of the cut tiles: the sum of a tile's partial slots in slot order (the order of the
+// tile's stage units), written like the staged kernel's own output.  Grid: (patch, tile);
+// workgroups of tiles that were not cut return at once.
+template <int BR, int BC, int MH>
+__global__ __launch_bounds__(256) void k_add_slots(const int2* __restrict__ tile_split,
+                                                   const float* __restrict__ partial,
+                                                   float* __restrict__ out, int n_patches,
+                                                   int ncc, int nx, int ny, int out_len) {
+  constexpr int TPR = BC / 16, RW = BR / 4, NT = RW * TPR, TM = 16 * MH;
+  constexpr long long PS = (long long)BR * BC * TM;  // floats per slot and patch
+  const int tile = blockIdx.y;
+  const int2 sp = tile_split[tile];
+  if (sp.x < 2) return;
+  const int py0 = (blockIdx.x / ncc) * BR, px0 = (blockIdx.x % ncc) * BC;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int n = lane % 16, g = lane / 16;
+  const float* base = partial + ((long long)sp.y * n_patches + blockIdx.x) * PS;
+  const long long stride = (long long)n_patches * PS;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int py = py0 + wave * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
+    if (py >= ny || px >= nx) continue;
+    const int local = (wave * RW + t / TPR) * BC + (t % TPR) * 16 + n;
+    float* o = out + ((long long)py * nx + px) * out_len;
+#pragma unroll
+    for (int h = 0; h < MH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * h + 4 * g + i, row = TM * tile + r;
+        if (row >= out_len) continue;
+        const long long e = (long long)local * TM + r;
+        float v = base[e];
+        for (int j = 1; j < sp.x; ++j) v += base[j * stride + e];
+        o[row] = v;
       }
   }
 }
@@ -394,15 +443,37 @@ const Layout& layout_for(const Model& m, bool adjoint, int dtype) {
   return adjoint ? m.s8a : m.s8f;
 }
 
-size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
+namespace {
+
+// The stage buffer of an apply: the padded input, then, for a staged layout with cut tiles,
+// the partial slots [slot][patch][position of the patch][TM rows] (FP32).
+struct StageParts {
+  size_t input = 0, partial = 0;
+};
+
+StageParts stage_parts(const Model& m, bool adjoint, int dtype) {
   const Layout& lay = layout_for(m, adjoint, dtype);
-  return (size_t)round_up(lay.in.elems() * elem_bytes(dtype), 256);
+  StageParts p;
+  p.input = (size_t)round_up(lay.in.elems() * elem_bytes(dtype), 256);
+  if (dtype != AROAM_FP64 && lay.n_slots > 0) {
+    p.partial = (size_t)lay.n_slots * lay.n_patches * lay.TM * kPatchRows * kPatchCols *
+                sizeof(float);
+  }
+  return p;
+}
+
+}  // namespace
+
+size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
+  const StageParts p = stage_parts(m, adjoint, dtype);
+  return p.input + p.partial;
 }
 
 namespace {
 
 template <typename T, bool FP8A, int MH>
-int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out, hipStream_t st) {
+int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* partial, void* out,
+                  hipStream_t st) {
   static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
   AROAM_CHECK(lay.TM == 16 * MH, AROAM_EINVAL, "tile height mismatch");
   auto kern = k_apply_staged<T, kPatchRows, kPatchCols, FP8A, MH>;
@@ -415,7 +486,10 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out,
   AROAM_CHECK(lay.lds_bytes <= 160 * 1024, AROAM_EINVAL,
               "lateral footprint too wide for the LDS stage (%zu bytes)", lay.lds_bytes);
   StagedArgs a;
-  a.tile_units = lay.d_tile_units;
+  a.pieces = lay.d_pieces;
+  a.tile_split = lay.d_tile_split;
+  a.partial = partial;
+  a.n_patches = lay.n_patches;
   a.units = lay.d_units;
   a.urows = lay.d_ucols;
   a.meta = lay.d_meta;
@@ -430,9 +504,17 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, void* out,
   a.NCOL = lay.NCOL;
   a.CS = lay.CS;
   AROAM_CHECK(lay.CH == 4 * (int)(16 / sizeof(T)), AROAM_EINVAL, "chunk length mismatch");
-  const dim3 grid((unsigned)(ceil_div(lay.in.ny, kPatchRows) * a.ncc), (unsigned)lay.n_tiles);
+  AROAM_CHECK(lay.n_patches == ceil_div(lay.in.ny, kPatchRows) * a.ncc, AROAM_EINVAL,
+              "patch count mismatch");
+  AROAM_CHECK(lay.n_slots == 0 || partial, AROAM_EINVAL, "no partial slots for a cut layout");
+  const dim3 grid((unsigned)lay.n_patches, (unsigned)lay.n_pieces);
   hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const void*)pk.d,
                      (const float*)pk.d_scale, (const T*)buf, (float*)out, a);
+  if (lay.n_slots > 0)
+    hipLaunchKernelGGL((k_add_slots<kPatchRows, kPatchCols, MH>),
+                       dim3((unsigned)lay.n_patches, (unsigned)lay.n_tiles), dim3(256), 0, st,
+                       lay.d_tile_split, (const float*)partial, (float*)out, lay.n_patches, a.ncc,
+                       a.nx, a.ny, a.out_len);
   return AROAM_OK;
 }
 
@@ -464,12 +546,16 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
     const dim3 grid((unsigned)a.n_ntiles, (unsigned)lay.n_tiles);
     hipLaunchKernelGGL(k_apply_fma<double>, grid, dim3(256), 0, st, (const double*)pk.d,
                        (const double*)buf, (double*)out, a, lay.G);
-  } else if (dtype == AROAM_FP32) {
-    AROAM_TRY((launch_staged<float, false, 1>(lay, pk, buf, out, st)));
-  } else if (dtype == AROAM_BF16) {
-    AROAM_TRY((launch_staged<uint16_t, false, kTileRows8 / 16>(lay, pk, buf, out, st)));
   } else {
-    AROAM_TRY((launch_staged<uint16_t, true, kTileRows8 / 16>(lay, pk, buf, out, st)));
+    const StageParts sp = stage_parts(m, adjoint, dtype);
+    float* partial =
+        sp.partial > 0 ? reinterpret_cast<float*>(static_cast<char*>(buf) + sp.input) : nullptr;
+    if (dtype == AROAM_FP32)
+      AROAM_TRY((launch_staged<float, false, 1>(lay, pk, buf, partial, out, st)));
+    else if (dtype == AROAM_BF16)
+      AROAM_TRY((launch_staged<uint16_t, false, kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
+    else
+      AROAM_TRY((launch_staged<uint16_t, true, kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
   }
   AROAM_HIP(hipGetLastError());
   if (!stage) AROAM_HIP(hipFreeAsync(buf, st));

@@ -125,6 +125,15 @@ int aroam_model_query(const aroam_model* model, aroam_model_info* info) {
   info->dtype_mask = m.dtype_mask;
   info->stored_columns = m.n_stored;
   info->stored_nnz = m.nnz_stored;
+  for (int d = 0; d < 4; ++d) {
+    const bool packed = (m.dtype_mask >> d) & 1u;
+    const aroam::Layout& f = aroam::layout_for(m, false, d);
+    const aroam::Layout& a = aroam::layout_for(m, true, d);
+    info->row_tiles[d] = packed ? f.n_tiles : 0;
+    info->row_tiles_adj[d] = packed ? a.n_tiles : 0;
+    info->pieces[d] = packed ? (f.staged ? f.n_pieces : f.n_tiles) : 0;
+    info->pieces_adj[d] = packed ? (a.staged ? a.n_pieces : a.n_tiles) : 0;
+  }
   return AROAM_OK;
 }
 

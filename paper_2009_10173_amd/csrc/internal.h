@@ -93,6 +93,17 @@ struct Layout {
   int4* d_units = nullptr;       // [n_units] (dy, chunk start, bundle begin, bundle end)
   int2* d_ucols = nullptr;       // [n_units] padded input rows [lo, hi) the unit loads (ring)
   size_t lds_bytes = 0;
+  // Work split of the staged kernel: a tile's stage units may be cut at chunk starts (where
+  // the LDS ring is reloaded anyway) into pieces of similar work, so that the workgroups of a
+  // launch are many and even, and the pieces may be dispatched heaviest first.  Each piece of a
+  // cut tile leaves its partial sums in a slot of the stage buffer, and a second kernel adds
+  // a tile's slots in slot order (deterministic).
+  int n_pieces = 0;
+  int n_slots = 0;               // partial slots (pieces of the tiles cut into several)
+  int n_patches = 0;             // position patches of one launch
+  int4* d_pieces = nullptr;      // [n_pieces] (tile, unit begin, unit end, slot or -1) in
+                                 // dispatch order
+  int2* d_tile_split = nullptr;  // [n_tiles] (pieces of the tile, its first slot)
 };
 
 struct Pack {

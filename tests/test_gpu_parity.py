@@ -94,6 +94,34 @@ def test_forward_adjoint_fp32(name):
     assert rel_l2(xa, oops.adjoint(H, y.astype(np.float32))) <= 1e-5
 
 
+def test_cut_tiles_match_oracle_elementwise():
+    """Staged layouts whose heavy tiles are cut into pieces, with the pieces' partial sums added
+    in a fixed order by a second kernel.  The small grids launch far fewer workgroups than the
+    chip holds, so cutting shortens their launches and the planner cuts some of their FP32
+    layouts; those applies match the oracle element by element."""
+    cut = 0
+    for name in SMALL:
+        cfg = W.config(name)
+        m = gpu_model(name)
+        info = m.info()
+        fp32 = P.DTYPES["fp32"]
+        fwd_cut = info["pieces"][fp32] > info["row_tiles"][fp32]
+        adj_cut = info["pieces_adj"][fp32] > info["row_tiles_adj"][fp32]
+        print(f"[{name}] fp32 pieces {info['pieces'][fp32]}/{info['row_tiles'][fp32]} forward, "
+              f"{info['pieces_adj'][fp32]}/{info['row_tiles_adj'][fp32]} adjoint", flush=True)
+        H = oracle_table(name)
+        if fwd_cut:
+            x = W.random_image(cfg, 21)
+            s = m.forward(t32(x), "fp32").cpu().numpy()
+            assert rel_max(s, oops.forward(H, x.astype(np.float32))) <= 1e-5
+        if adj_cut:
+            y = W.random_signal(cfg, 21)
+            xa = m.adjoint(t32(y), "fp32").cpu().numpy()
+            assert rel_max(xa, oops.adjoint(H, y.astype(np.float32))) <= 1e-5
+        cut += fwd_cut + adj_cut
+    assert cut > 0, "no small FP32 layout was cut"
+
+
 @pytest.mark.parametrize("name", SMALL)
 def test_forward_adjoint_bf16_reported(name):
     """BF16 operands with FP32 accumulation: error vs the FP64 oracle is reported; the
@@ -143,6 +171,10 @@ def test_full_size_depth_slabs_fp32():
     cfg = W.config(name)
     g = cfg["grid"]
     m = gpu_model(name, ("fp32",))
+    info = m.info()
+    fp32 = P.DTYPES["fp32"]
+    print(f"[{name}] fp32 pieces {info['pieces'][fp32]}/{info['row_tiles'][fp32]} forward, "
+          f"{info['pieces_adj'][fp32]}/{info['row_tiles_adj'][fp32]} adjoint", flush=True)
     ks = [23, 90]
     Hs = omodel.build_depth_slabs(cfg["sensor"], g, ks)
     rng = W.rng(77)
