@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 
 #include "internal.h"
@@ -400,16 +401,17 @@ __global__ __launch_bounds__(256) void k_add_slots(const int2* __restrict__ tile
     const int local = (wave * RW + t / TPR) * BC + (t % TPR) * 16 + n;
     float* o = out + ((long long)py * nx + px) * out_len;
 #pragma unroll
-    for (int h = 0; h < MH; ++h)
+    for (int h = 0; h < MH; ++h) {
+      // four consecutive rows per lane: 16-byte loads and stores
+      const long long e = (long long)local * TM + 16 * h + 4 * g;
+      floatx4 v = *reinterpret_cast<const floatx4*>(base + e);
+      for (int j = 1; j < sp.x; ++j) v += *reinterpret_cast<const floatx4*>(base + j * stride + e);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = 16 * h + 4 * g + i, row = TM * tile + r;
-        if (row >= out_len) continue;
-        const long long e = (long long)local * TM + r;
-        float v = base[e];
-        for (int j = 1; j < sp.x; ++j) v += base[j * stride + e];
-        o[row] = v;
+        const int row = TM * tile + 16 * h + 4 * g + i;
+        if (row < out_len) o[row] = v[i];
       }
+    }
   }
 }
 
@@ -477,11 +479,15 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
   static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
   AROAM_CHECK(lay.TM == 16 * MH, AROAM_EINVAL, "tile height mismatch");
   auto kern = k_apply_staged<T, kPatchRows, kPatchCols, FP8A, MH>;
-  static bool attr_set = false;  // allow the full LDS of a CU for wide footprints
-  if (!attr_set) {
+  // allow the full LDS of a CU for wide footprints, once per device
+  static std::atomic<unsigned long long> attr_set{0};
+  int dev = 0;
+  AROAM_HIP(hipGetDevice(&dev));
+  const unsigned long long bit = 1ull << (dev & 63);
+  if (!(attr_set.load() & bit)) {
     AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024));
-    attr_set = true;
+    attr_set.fetch_or(bit);
   }
   AROAM_CHECK(lay.lds_bytes <= 160 * 1024, AROAM_EINVAL,
               "lateral footprint too wide for the LDS stage (%zu bytes)", lay.lds_bytes);

@@ -10,13 +10,12 @@
 
 #include <algorithm>
 #include <cmath>
-#include <functional>
-#include <queue>
 #include <cstdio>
 #include <cstring>
 #include <vector>
 
 #include "internal.h"
+#include "plan.h"
 
 namespace aroam {
 
@@ -581,123 +580,24 @@ std::vector<UnitEntry> order_unit(const std::vector<UnitEntry>& in, int maxcol, 
   return out;
 }
 
-// Finishing time of a launch whose workgroups (every patch of each piece, pieces in the given
-// order) take the first of `slots` free places and last as long as their work.
-double simulate_launch(const std::vector<double>& piece_work, int n_patches, int slots) {
-  std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
-  for (int i = 0; i < slots; ++i) free_at.push(0.0);
-  double end = 0;
-  for (double w : piece_work)
-    for (int p = 0; p < n_patches; ++p) {
-      const double t = free_at.top() + w;
-      free_at.pop();
-      free_at.push(t);
-      end = std::max(end, t);
-    }
-  return end;
-}
-
-// Cut the tiles' stage units into pieces (see Layout).  For D = 1 .. 8 every tile is cut into
-// about (its work) / (largest tile work / D) pieces of similar work at chunk starts, and the
-// pieces are dispatched in tile order or heaviest first, whichever the simulation finishes
-// sooner; the work of a unit is the MFMA row halves it issues.  A
-// cut (D > 1) is taken only where `allow_cut` and its simulated launch (three workgroups per
-// compute unit) is at least 10 % shorter than the uncut one: the partial slots cost HBM
-// traffic and a second launch, which the FP32 kernels hide and the BF16 / FP8 kernels (about
-// seven times shorter) do not.  The partial slots are capped at 1 GiB.
+// Plan the staged launch of a layout (plan.h) and upload the pieces.  Cuts are allowed for
+// the FP32 layouts only: the partial slots cost HBM traffic and a second launch, which the
+// FP32 kernels hide and the BF16 / FP8 kernels (about seven times shorter) do not.  The
+// partial slots are capped at 1 GiB.
 int plan_pieces(Layout& lay, const std::vector<int>& tile_units,
                 const std::vector<std::vector<int>>& chunk_starts,
                 const std::vector<double>& unit_work, int slots, bool allow_cut,
                 size_t& bytes) {
-  const int nT = lay.n_tiles;
-  std::vector<double> prefix(unit_work.size() + 1, 0.0);
-  for (size_t u = 0; u < unit_work.size(); ++u) prefix[u + 1] = prefix[u] + unit_work[u];
-  double wmax = 0;
-  for (int t = 0; t < nT; ++t)
-    wmax = std::max(wmax, prefix[tile_units[t + 1]] - prefix[tile_units[t]]);
-  struct Piece {
-    int tile, u0, u1;
-    double w;
-  };
-  auto cut = [&](int D, std::vector<Piece>& out, std::vector<int>& npieces) {
-    out.clear();
-    npieces.assign(nT, 1);
-    for (int t = 0; t < nT; ++t) {
-      const int a = tile_units[t], b = tile_units[t + 1];
-      const double wt = prefix[b] - prefix[a];
-      const std::vector<int>& cs = chunk_starts[t];  // cs[0] == a when the tile has units
-      int S = 1;
-      if (D > 1 && wt > 0 && wmax > 0)
-        S = std::max(1, std::min((int)cs.size(), (int)std::lround(wt * D / wmax)));
-      // cut k of S at the chunk start whose prefix work is nearest to k/S of the tile's
-      std::vector<int> cuts;
-      size_t j = 1;
-      for (int k = 1; k < S && j < cs.size(); ++k, ++j) {
-        const double goal = prefix[a] + wt * k / S;
-        while (j + 1 < cs.size() &&
-               std::fabs(prefix[cs[j + 1]] - goal) <= std::fabs(prefix[cs[j]] - goal))
-          ++j;
-        cuts.push_back(cs[j]);
-      }
-      cuts.push_back(b);
-      int u = a;
-      for (int v : cuts) {
-        out.push_back(Piece{t, u, v, prefix[v] - prefix[u]});
-        u = v;
-      }
-      npieces[t] = (int)cuts.size();  // a tile without units keeps one piece that writes zeros
-    }
-  };
-  auto launch_time = [&](const std::vector<Piece>& order) {
-    std::vector<double> w;
-    for (const Piece& p : order) w.push_back(p.w + 1.0);
-    return simulate_launch(w, lay.n_patches, slots);
-  };
-  const double per_slot_bytes = (double)lay.TM * kPatchRows * kPatchCols * sizeof(float);
-  std::vector<Piece> best, cur;
-  std::vector<int> best_np, cur_np;
-  double best_time = 0, uncut = 0;
-  for (int D = 1; D <= (allow_cut ? 8 : 1); ++D) {
-    cut(D, cur, cur_np);
-    long long nslots = 0;
-    for (int t = 0; t < nT; ++t) nslots += cur_np[t] > 1 ? cur_np[t] : 0;
-    if (D > 1 && nslots * lay.n_patches * per_slot_bytes > (double)(1ll << 30)) break;
-    // dispatch order: tile order or heaviest first, whichever finishes sooner
-    std::vector<Piece> heavy = cur;
-    std::stable_sort(heavy.begin(), heavy.end(),
-                     [](const Piece& x, const Piece& y) { return x.w > y.w; });
-    double time = launch_time(cur);
-    const double time_heavy = launch_time(heavy);
-    if (time_heavy <= time) {
-      time = time_heavy;
-      cur.swap(heavy);
-    }
-    if (D == 1) uncut = time;
-    if (D == 1 || (time < 0.9 * uncut && time < best_time)) {
-      best_time = time;
-      best = cur;
-      best_np = cur_np;
-    }
-  }
-  std::vector<int2> split(nT);
-  int nslots = 0;
-  for (int t = 0; t < nT; ++t) {
-    split[t] = make_int2(best_np[t], best_np[t] > 1 ? nslots : -1);
-    if (best_np[t] > 1) nslots += best_np[t];
-  }
-  std::vector<int> seen(nT, 0);
+  const double slot_bytes = (double)lay.TM * kPatchRows * kPatchCols * sizeof(float);
+  const LaunchPlan plan = plan_launch(tile_units, chunk_starts, unit_work, lay.n_patches, slots,
+                                      allow_cut, slot_bytes, (double)(1ll << 30));
   std::vector<int4> pieces;
-  // slots of a tile's pieces in unit order, so that the partial sums are added in that order
-  std::vector<Piece> by_unit = best;
-  std::stable_sort(by_unit.begin(), by_unit.end(),
-                   [](const Piece& x, const Piece& y) { return x.u0 < y.u0; });
-  std::vector<int> slot_of_u0(tile_units.back() + 1, -1);
-  for (const Piece& p : by_unit)
-    if (best_np[p.tile] > 1) slot_of_u0[p.u0] = split[p.tile].y + seen[p.tile]++;
-  for (const Piece& p : best)
-    pieces.push_back(make_int4(p.tile, p.u0, p.u1, best_np[p.tile] > 1 ? slot_of_u0[p.u0] : -1));
+  for (const PlanPiece& p : plan.pieces) pieces.push_back(make_int4(p.tile, p.u0, p.u1, p.slot));
+  std::vector<int2> split(lay.n_tiles);
+  for (int t = 0; t < lay.n_tiles; ++t)
+    split[t] = make_int2(plan.tile_pieces[t], plan.tile_first_slot[t]);
   lay.n_pieces = (int)pieces.size();
-  lay.n_slots = nslots;
+  lay.n_slots = plan.n_slots;
   AROAM_TRY(alloc_copy(&lay.d_pieces, pieces, bytes));
   AROAM_TRY(alloc_copy(&lay.d_tile_split, split, bytes));
   return AROAM_OK;
