@@ -110,8 +110,8 @@ struct StagedArgs {
   int NCOL, CS;
 };
 
-// Table operand of one bundle for one lane: 16 bytes (FP32 / BF16) or 8 bytes of e4m3 plus
-// the K-group's scale.
+// Table operand of one bundle for one lane: 16 bytes per half (FP32 / BF16), or 8 bytes of
+// e4m3 per half (both halves in one 16-byte load) plus the K-group's scale per half.
 // MH 16-row halves of the tile (MH = TM / 16).
 template <typename T, bool FP8A, int MH>
 struct AFrag {
@@ -128,15 +128,20 @@ __device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
                                        const int* __restrict__ bmask, int b, int g, int n,
                                        AFrag<T, FP8A, MH>& f) {
   const int q = b * kLaneGroups + g;
+  if constexpr (FP8A) {
+    // e4m3: the lane's 8 entries of both halves in one 16-byte load, both scales in one
+    static_assert(MH == 2, "FP8 tiles have two 16-row halves");
+    const u32x4 r = *reinterpret_cast<const u32x4*>(reinterpret_cast<const uint8_t*>(pack_raw) +
+                                                    ((long long)q * 16 + n) * 16);
+    const floatx2 sc = *reinterpret_cast<const floatx2*>(gscale + (long long)q * 2);
+    f.v[0] = u32x4{r.x, r.y, 0u, 0u};
+    f.v[1] = u32x4{r.z, r.w, 0u, 0u};
+    f.sc[0] = sc.x;
+    f.sc[1] = sc.y;
+  } else {
 #pragma unroll
-  for (int h = 0; h < MH; ++h) {
-    const long long row = (long long)q * (16 * MH) + 16 * h + n;
-    if constexpr (FP8A) {
-      const u32x2 r8 = *reinterpret_cast<const u32x2*>(
-          reinterpret_cast<const uint8_t*>(pack_raw) + row * 8);
-      f.v[h] = u32x4{r8.x, r8.y, 0u, 0u};
-      f.sc[h] = gscale[q * MH + h];
-    } else {
+    for (int h = 0; h < MH; ++h) {
+      const long long row = (long long)q * (16 * MH) + 16 * h + n;
       constexpr int VEC = 16 / sizeof(T);
       f.v[h] = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(pack_raw) + row * VEC);
       f.sc[h] = 1.0f;

@@ -321,7 +321,9 @@ __global__ void k_pack_fp8(long long total, int G, int TM, bool adjoint,
       n = gd.y + j;
     }
     const double v = table_value(gd.x, n, k, nz, nt, colidx, lo, off, band);
-    pack[idx] = sc > 0.0f ? f32_to_e4m3((float)(v / sc)) : (uint8_t)0;
+    // a lane's entries of both 16-row halves are adjacent: [group][row in half][half][G]
+    const long long pos = grp * TM * G + (long long)((m % 16) * NH + h) * G + j;
+    pack[pos] = sc > 0.0f ? f32_to_e4m3((float)(v / sc)) : (uint8_t)0;
   }
 }
 
