@@ -355,6 +355,25 @@ def test_fista_bf16_anchored_matches_oracle(name, period, warmup):
     assert e_a <= 1e-4
 
 
+@pytest.mark.parametrize("name,period,warmup", [("pairs16", 2, 50), ("mid7", 2, 15)])
+def test_fista_fp8_anchored_matches_oracle(name, period, warmup):
+    """e4m3 correction applies with FP32 anchor gradients.  Between anchors the corrections
+    carry the e4m3 apply error (a few 1e-2 relative), so plain FP8 FISTA ends about 1e-1 from
+    the FP64 oracle; with an anchor every second iteration after the warm-up the error must
+    fall by two orders of magnitude and stay within 1e-3."""
+    m = gpu_model(name)
+    iters = 200 if name == "pairs16" else 60
+    s, L, lam, x_ref = _fista_ref(name, iters)
+    x, _ = m.solve_l1(t32(s), lam=lam, iters=iters, inner="fp8", outer="fp32", lipschitz=L,
+                      anchor_period=period, anchor_warmup=warmup)
+    xb, _ = m.solve_l1(t32(s), lam=lam, iters=iters, inner="fp8", lipschitz=L)
+    e_a = rel_l2(x.cpu().numpy(), x_ref)
+    e_b = rel_l2(xb.cpu().numpy(), x_ref)
+    print(f"[fista fp8 {name}] plain fp8 {e_b:.2e} anchored {e_a:.2e}")
+    assert e_a <= e_b / 100
+    assert e_a <= 1e-3
+
+
 @pytest.mark.parametrize("name", SMALL)
 def test_forward_adjoint_fp8_reported(name):
     """e4m3 table with one FP32 scale per (offset, 16-depth block), BF16 vector operands, FP32
