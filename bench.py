@@ -147,8 +147,9 @@ def main():
     log(f"building model {args.workload}")
     torch.cuda.synchronize()
     t0 = time.time()
-    lo = "fp8" if args.dtype == "fp8" else "bf16"    # inner precision of the refined leg
-    model = P.Model(cfg["sensor"], g, dtypes=tuple(sorted({"fp32", args.dtype, lo})))
+    # inner precisions of the refined legs: BF16 and FP8 for the FP32 bench, else its own
+    lows = ["bf16", "fp8"] if args.dtype == "fp32" else [args.dtype]
+    model = P.Model(cfg["sensor"], g, dtypes=tuple(sorted({"fp32", args.dtype, *lows})))
     torch.cuda.synchronize()
     t_build = time.time() - t0
     info = model.info()
@@ -220,29 +221,30 @@ def main():
                      "frac": achieved / peak, "issued_frac": mfma_issued,
                      "traffic": profiled_traffic(args.workload, args.dtype, dom)},
     }
-    # reduced precision with refinement on the same workload: BF16 (FP8 when the main leg is
-    # FP8) applies, FP32 residuals, two sweeps
-    log(f"{lo}-refined reconstruction (2 sweeps)")
+    # reduced precision with refinement on the same workload: BF16 / FP8 applies, FP32
+    # residuals, two sweeps
     x32 = x if args.dtype == "fp32" else model.solve_lsqr(s, lam=-1.0, iters=iters)[0]
-    model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32", refine_sweeps=2)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    xr, rinfo = model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32",
-                                 refine_sweeps=2)
-    torch.cuda.synchronize()
-    t_ref = time.perf_counter() - t1
-    diff = ((xr - x32).norm() / x32.norm()).item()
-    kt_lo = kernel_times(model, lo, x0, s, args.kernel_reps)
-    li = P.DTYPES[lo]
-    result[f"{lo}_refined"] = {
-        "recon_ms": t_ref * 1e3, "sweeps": 2,
-        "pairs_per_s": ((iters + 0.5) * 3 + 2 + 0.5) / t_ref,
-        "rel_diff_vs_fp32_recon": diff,
-        "kernel_ms": kt_lo,
-        f"issued_frac_{lo}": {k: 2.0 * (info["mac_exec"][li] if k == "forward" else
-                                        info["mac_exec_adj"][li]) / (v * 1e-3) / 1e12
-                              / ISSUE_PEAK[lo] for k, v in kt_lo.items()},
-    }
+    for lo in lows:
+        log(f"{lo}-refined reconstruction (2 sweeps)")
+        model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32", refine_sweeps=2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xr, rinfo = model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32",
+                                     refine_sweeps=2)
+        torch.cuda.synchronize()
+        t_ref = time.perf_counter() - t1
+        diff = ((xr - x32).norm() / x32.norm()).item()
+        kt_lo = kernel_times(model, lo, x0, s, args.kernel_reps)
+        li = P.DTYPES[lo]
+        result[f"{lo}_refined"] = {
+            "recon_ms": t_ref * 1e3, "sweeps": 2,
+            "pairs_per_s": ((iters + 0.5) * 3 + 2 + 0.5) / t_ref,
+            "rel_diff_vs_fp32_recon": diff,
+            "kernel_ms": kt_lo,
+            f"issued_frac_{lo}": {k: 2.0 * (info["mac_exec"][li] if k == "forward" else
+                                            info["mac_exec_adj"][li]) / (v * 1e-3) / 1e12
+                                  / ISSUE_PEAK[lo] for k, v in kt_lo.items()},
+        }
     if args.serve_requests > 0:
         log(f"serving leg: {args.serve_requests} mixed requests")
         model.close()
