@@ -81,7 +81,7 @@ struct Layout {
   int* d_meta = nullptr;         // [n_bundles * 4] per K-group offset (see above)
   int* d_bmask = nullptr;        // staged form: [n_bundles] 16-row halves the bundle reaches
   int4* d_groups = nullptr;      // [n_bundles * 4] (offset index, start, tile, active)
-  std::vector<int> h_tile_start;
+  std::vector<int> h_tile_start;  // bundle (direct) or stage-unit (staged) range of each tile
   long long mac_exec = 0;        // MACs issued per apply
   PadGeom in;                    // staged input geometry
   // LDS-staged form
@@ -89,7 +89,6 @@ struct Layout {
   int CH = 0, BR = 0, BC = 0;    // chunk length, patch rows, patch columns
   int CS = 0, NCOL = 0;          // LDS column stride (elements), staged columns BC + 2K
   long long n_units = 0;
-  int* d_tile_units = nullptr;   // [n_tiles + 1] stage-unit range of each tile
   int4* d_units = nullptr;       // [n_units] (dy, chunk start, bundle begin, bundle end)
   int2* d_ucols = nullptr;       // [n_units] padded input rows [lo, hi) the unit loads (ring)
   size_t lds_bytes = 0;

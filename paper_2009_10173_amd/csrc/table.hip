@@ -703,7 +703,6 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   lay.mac_exec = halves * kLaneGroups * kTile * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
   AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
               "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
-  AROAM_TRY(alloc_copy(&lay.d_tile_units, tile_units, bytes));
   AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
   AROAM_TRY(alloc_copy(&lay.d_ucols, urows, bytes));
   AROAM_TRY(alloc_copy(&lay.d_meta, meta, bytes));
@@ -1218,8 +1217,10 @@ int finish_model(Model* m, int rc, unsigned mask, hipStream_t st, Model** out) {
   size_t b = (size_t)std::max<long long>(1, m->nnz_stored) * sizeof(double);
   b += m->h_colidx.size() * sizeof(int) + m->n_stored * sizeof(int) + m->h_off.size() * 8;
   for (const Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a})
-    b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) + l->h_tile_start.size() * 4 +
-         (l->staged ? l->n_bundles * sizeof(int) : 0) +
+    b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) +
+         (l->staged ? l->n_bundles * sizeof(int) + l->n_pieces * sizeof(int4) +
+                          l->n_tiles * sizeof(int2)
+                    : l->h_tile_start.size() * sizeof(int)) +
          l->n_units * (sizeof(int4) + sizeof(int2));
   for (int d = 0; d < 4; ++d) b += m->fwd_pack[d].bytes + m->adj_pack[d].bytes;
   m->device_bytes = b;
@@ -1241,7 +1242,6 @@ void destroy_model(Model* m) {
     (void)hipFree(l->d_meta);
     (void)hipFree(l->d_bmask);
     (void)hipFree(l->d_groups);
-    (void)hipFree(l->d_tile_units);
     (void)hipFree(l->d_pieces);
     (void)hipFree(l->d_tile_split);
     (void)hipFree(l->d_units);
