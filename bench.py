@@ -214,6 +214,13 @@ def main():
         "fill": {"forward": info["mac_alg"] / info["mac_exec"][di],
                  "adjoint": info["mac_alg"] / info["mac_exec_adj"][di]},
         "table_build_s": t_build,
+        # workgroup rows of each staged launch: output row tiles, and pieces where the launch
+        # plan cuts heavy tiles
+        "launch": {dt: {"forward": {"tiles": info["row_tiles"][P.DTYPES[dt]],
+                                    "pieces": info["pieces"][P.DTYPES[dt]]},
+                        "adjoint": {"tiles": info["row_tiles_adj"][P.DTYPES[dt]],
+                                    "pieces": info["pieces_adj"][P.DTYPES[dt]]}}
+                   for dt in sorted({"fp32", args.dtype, *lows})},
         "lambda": sinfo["lam"],
         "roofline": {"bound": "mfma", "kernel": (f"{dom} (e4m3 table, bf16 MFMA)" if args.dtype == "fp8"
                                 else f"{dom} ({args.dtype} MFMA)"),

@@ -582,17 +582,14 @@ std::vector<UnitEntry> order_unit(const std::vector<UnitEntry>& in, int maxcol, 
   return out;
 }
 
-// Plan the staged launch of a layout (plan.h) and upload the pieces.  Cuts are allowed for
-// the FP32 layouts only: the partial slots cost HBM traffic and a second launch, which the
-// FP32 kernels hide and the BF16 / FP8 kernels (about seven times shorter) do not.  The
-// partial slots are capped at 1 GiB.
+// Plan the staged launch of a layout (plan.h) and upload the pieces.  The partial slots are
+// capped at 1 GiB.
 int plan_pieces(Layout& lay, const std::vector<int>& tile_units,
                 const std::vector<std::vector<int>>& chunk_starts,
-                const std::vector<double>& unit_work, int slots, bool allow_cut,
-                size_t& bytes) {
+                const std::vector<double>& unit_work, int slots, size_t& bytes) {
   const double slot_bytes = (double)lay.TM * kPatchRows * kPatchCols * sizeof(float);
   const LaunchPlan plan = plan_launch(tile_units, chunk_starts, unit_work, lay.n_patches, slots,
-                                      allow_cut, slot_bytes, (double)(1ll << 30));
+                                      /*allow_cut=*/true, slot_bytes, (double)(1ll << 30));
   std::vector<int4> pieces;
   for (const PlanPiece& p : plan.pieces) pieces.push_back(make_int4(p.tile, p.u0, p.u1, p.slot));
   std::vector<int2> split(lay.n_tiles);
@@ -712,8 +709,7 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   lay.n_patches = (int)(ceil_div(g.ny, BR) * ceil_div(g.nx, BC));
   int cus = 0;
   AROAM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m.device));
-  return plan_pieces(lay, tile_units, chunk_starts, unit_work, 3 * std::max(cus, 1),
-                     /*allow_cut=*/esize == 4, bytes);
+  return plan_pieces(lay, tile_units, chunk_starts, unit_work, 3 * std::max(cus, 1), bytes);
 }
 
 template <typename T>

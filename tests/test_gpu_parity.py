@@ -97,29 +97,33 @@ def test_forward_adjoint_fp32(name):
 def test_cut_tiles_match_oracle_elementwise():
     """Staged layouts whose heavy tiles are cut into pieces, with the pieces' partial sums added
     in a fixed order by a second kernel.  The small grids launch far fewer workgroups than the
-    chip holds, so cutting shortens their launches and the planner cuts some of their FP32
-    layouts; those applies match the oracle element by element."""
-    cut = 0
+    chip holds, so cutting shortens their launches and the planner cuts some of their layouts.
+    Cut FP32 applies match the oracle element by element (1e-5 of the largest entry); cut BF16
+    applies stay within the BF16 bound of the uncut ones (1e-2 relative L2)."""
+    cut = {"fp32": 0, "bf16": 0}
     for name in SMALL:
         cfg = W.config(name)
         m = gpu_model(name)
         info = m.info()
-        fp32 = P.DTYPES["fp32"]
-        fwd_cut = info["pieces"][fp32] > info["row_tiles"][fp32]
-        adj_cut = info["pieces_adj"][fp32] > info["row_tiles_adj"][fp32]
-        print(f"[{name}] fp32 pieces {info['pieces'][fp32]}/{info['row_tiles'][fp32]} forward, "
-              f"{info['pieces_adj'][fp32]}/{info['row_tiles_adj'][fp32]} adjoint", flush=True)
         H = oracle_table(name)
-        if fwd_cut:
-            x = W.random_image(cfg, 21)
-            s = m.forward(t32(x), "fp32").cpu().numpy()
-            assert rel_max(s, oops.forward(H, x.astype(np.float32))) <= 1e-5
-        if adj_cut:
-            y = W.random_signal(cfg, 21)
-            xa = m.adjoint(t32(y), "fp32").cpu().numpy()
-            assert rel_max(xa, oops.adjoint(H, y.astype(np.float32))) <= 1e-5
-        cut += fwd_cut + adj_cut
-    assert cut > 0, "no small FP32 layout was cut"
+        x = W.random_image(cfg, 21)
+        y = W.random_signal(cfg, 21)
+        for dt in ("fp32", "bf16"):
+            d = P.DTYPES[dt]
+            fwd_cut = info["pieces"][d] > info["row_tiles"][d]
+            adj_cut = info["pieces_adj"][d] > info["row_tiles_adj"][d]
+            print(f"[{name}] {dt} pieces {info['pieces'][d]}/{info['row_tiles'][d]} forward, "
+                  f"{info['pieces_adj'][d]}/{info['row_tiles_adj'][d]} adjoint", flush=True)
+            if fwd_cut:
+                s = m.forward(t32(x), dt).cpu().numpy()
+                ref = oops.forward(H, x.astype(np.float32))
+                assert (rel_max(s, ref) <= 1e-5) if dt == "fp32" else (rel_l2(s, ref) <= 1e-2)
+            if adj_cut:
+                xa = m.adjoint(t32(y), dt).cpu().numpy()
+                ref = oops.adjoint(H, y.astype(np.float32))
+                assert (rel_max(xa, ref) <= 1e-5) if dt == "fp32" else (rel_l2(xa, ref) <= 1e-2)
+            cut[dt] += fwd_cut + adj_cut
+    assert cut["fp32"] > 0 and cut["bf16"] > 0, f"layouts cut: {cut}"
 
 
 @pytest.mark.parametrize("name", SMALL)
