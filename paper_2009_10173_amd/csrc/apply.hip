@@ -541,7 +541,7 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
   const Pack& pk = adjoint ? m.adj_pack[dtype] : m.fwd_pack[dtype];
   const PadGeom& pg = lay.in;
   void* buf = stage;
-  if (!buf) AROAM_HIP(hipMallocAsync(&buf, stage_bytes(m, adjoint, dtype), st));
+  if (!buf) AROAM_TRY(pool_alloc(&buf, stage_bytes(m, adjoint, dtype), st));
   const dim3 sgrid((unsigned)(pg.nyp * pg.nxp));
   if (dtype == AROAM_FP64)
     hipLaunchKernelGGL((k_stage<double, double>), sgrid, dim3(256), 0, st, (const double*)in,

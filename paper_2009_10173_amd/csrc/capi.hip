@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -21,6 +23,34 @@ void set_error(const char* fmt, ...) {
 }
 
 void clear_error() { g_err[0] = 0; }
+
+int pool_alloc(void** p, size_t bytes, hipStream_t st) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static hipMemPool_t pools[kMaxDevices] = {};
+  int dev = 0;
+  AROAM_HIP(hipGetDevice(&dev));
+  AROAM_CHECK(dev >= 0 && dev < kMaxDevices, AROAM_EDEVICE, "device %d out of range", dev);
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!pools[dev]) {
+      hipMemPoolProps props = {};
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      hipMemPool_t created = nullptr;
+      AROAM_HIP(hipMemPoolCreate(&created, &props));
+      uint64_t keep = UINT64_MAX;  // keep every freed block for reuse
+      AROAM_HIP(hipMemPoolSetAttribute(created, hipMemPoolAttrReleaseThreshold, &keep));
+      pools[dev] = created;
+    }
+    pool = pools[dev];
+  }
+  AROAM_HIP(hipMallocFromPoolAsync(p, bytes, pool, st));
+  return AROAM_OK;
+}
 
 }  // namespace aroam
 

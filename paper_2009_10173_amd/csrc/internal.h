@@ -16,6 +16,12 @@ namespace aroam {
 void set_error(const char* fmt, ...);
 void clear_error();
 
+// Stream-ordered temporaries of the library (stage buffers of single applies, solver state):
+// one memory pool per device that keeps freed blocks for reuse (no release threshold), so
+// repeated applies and solves do not hand memory back to the driver at every
+// synchronisation.  The pools live until the process ends.  Free with hipFreeAsync.
+int pool_alloc(void** p, size_t bytes, hipStream_t st);
+
 #define AROAM_HIP(expr)                                                             \
   do {                                                                              \
     hipError_t e_ = (expr);                                                         \

@@ -435,7 +435,7 @@ class SolverT final : public Solver {
   double t_ = 1.0;
 
   int alloc_bytes(void** p, size_t b) {
-    AROAM_HIP(hipMallocAsync(p, std::max<size_t>(1, b), stream));
+    AROAM_TRY(pool_alloc(p, std::max<size_t>(1, b), stream));
     allocs_.push_back(*p);
     return AROAM_OK;
   }
