@@ -369,14 +369,17 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
     const int py = py0 + wave * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
     if (py >= a.ny || px >= a.nx) continue;
     const int local = (wave * RW + t / TPR) * BC + (t % TPR) * 16 + n;
-    float* o = slot ? slot + (long long)local * (16 * MH) - 16 * MH * tile
-                    : out + ((long long)py * a.nx + px) * a.out_len;
+    // element offset of output row `row` of this position: in the slot the rows of the tile
+    // start at 0, in the output at 0 of the position's column
+    float* dst = slot ? slot : out;
+    const long long off = slot ? (long long)local * (16 * MH) - 16 * MH * tile
+                               : ((long long)py * a.nx + px) * a.out_len;
 #pragma unroll
     for (int h = 0; h < MH; ++h)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = 16 * MH * tile + 16 * h + 4 * g + i;
-        if (row < a.out_len) o[row] = acc[h][t][i];
+        if (row < a.out_len) dst[off + row] = acc[h][t][i];
       }
   }
 }
