@@ -170,21 +170,22 @@ struct StageAddr {
   int lds;
 };
 
-template <int BR>
+// RS: slots of the LDS row ring (padded row G lives in slot G mod RS).
+template <int RS>
 __device__ __forceinline__ StageAddr stage_addr(const StagedArgs& a, int lo, int e0, int idx,
                                                 int py0, int px0, int rowvec, int nvec, int vec) {
   const int G = lo + idx / rowvec;
   const int rem = idx % rowvec;
   const int c = rem / nvec, v = rem % nvec;
   StageAddr r;
-  r.lds = ((G % BR) * a.NCOL + c) * a.CS + v * vec;
+  r.lds = ((G % RS) * a.NCOL + c) * a.CS + v * vec;
   r.src = ((long long)(py0 + G) * a.nxp + (px0 + c)) * a.Lp + e0 + v * vec;
   return r;
 }
 
 // Fetch up to 256 * PF stage vectors of unit u into registers (the rest is loaded when the
-// unit starts); pf_off = -1 marks an unused slot.
-template <typename T, int BR, int PF>
+// unit's rows are written); pf_off = -1 marks an unused slot.
+template <typename T, int RS, int PF>
 __device__ __forceinline__ void stage_prefetch(const StagedArgs& a, const T* __restrict__ in,
                                                int u, int py0, int px0, int rowvec, int nvec,
                                                u32x4 (&pf)[PF], int (&pf_off)[PF]) {
@@ -197,10 +198,42 @@ __device__ __forceinline__ void stage_prefetch(const StagedArgs& a, const T* __r
     const int idx = threadIdx.x + 256 * i;
     pf_off[i] = -1;
     if (idx < nv) {
-      const StageAddr sa = stage_addr<BR>(a, Rr.x, U.y, idx, py0, px0, rowvec, nvec, VEC);
+      const StageAddr sa = stage_addr<RS>(a, Rr.x, U.y, idx, py0, px0, rowvec, nvec, VEC);
       pf_off[i] = sa.lds;
       pf[i] = *reinterpret_cast<const u32x4*>(in + sa.src);
     }
+  }
+}
+
+// Write the rows unit u adds to the LDS ring: the prefetched vectors, then the rest (a full
+// ring reload) with four loads in flight per thread.
+template <typename T, int RS, int PF>
+__device__ __forceinline__ void stage_rows(const StagedArgs& a, const T* __restrict__ in, T* lds,
+                                           int u, int py0, int px0, int rowvec, int nvec,
+                                           const u32x4 (&pf)[PF], const int (&pf_off)[PF]) {
+  constexpr int VEC = 16 / sizeof(T);
+#pragma unroll
+  for (int i = 0; i < PF; ++i)
+    if (pf_off[i] >= 0) *reinterpret_cast<u32x4*>(lds + pf_off[i]) = pf[i];
+  const int4 U = a.units[u];
+  const int2 Rr = a.urows[u];
+  const int nv = (Rr.y - Rr.x) * rowvec;
+  for (int base = 256 * PF; base < nv; base += 256 * 4) {
+    u32x4 tmp[4];
+    int off[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = base + threadIdx.x + 256 * i;
+      off[i] = -1;
+      if (idx < nv) {
+        const StageAddr sa = stage_addr<RS>(a, Rr.x, U.y, idx, py0, px0, rowvec, nvec, VEC);
+        off[i] = sa.lds;
+        tmp[i] = *reinterpret_cast<const u32x4*>(in + sa.src);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (off[i] >= 0) *reinterpret_cast<u32x4*>(lds + off[i]) = tmp[i];
   }
 }
 
@@ -277,52 +310,36 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
     for (int t = 0; t < NT; ++t) acc[h][t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int u0 = piece.y, u1 = piece.z;
   if (u0 < u1) {
+    // the ring has one slot more than the BR rows a unit reads: when the next unit adds the
+    // single row after the current unit's rows (consecutive row offsets in one chunk), that
+    // row goes to the free slot while other waves still read the current unit, and one
+    // barrier per unit suffices
+    constexpr int RS = BR + 1;
     u32x4 pf[PF];
     int pf_off[PF];
-    stage_prefetch<T, BR, PF>(a, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
     // table fragments stream through a ring of PD slots per stage unit, unrolled so that
     // every slot stays in fixed registers (shifting a ring would move registers that loads
     // in flight still target, which forces full waits)
     AFrag<T, FP8A, MH> ring[PD];
-    for (int u = u0; u < u1; ++u) {
-      const int4 U = a.units[u];
-      const int2 Rr = a.urows[u];
-      // slot j holds bundle U.z + j (mod PD); the first loads overlap the staging below
+    {
+      const int4 U = a.units[u0];
 #pragma unroll
       for (int j = 0; j < PD; ++j)
         load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(U.z + j, U.w - 1), g, n, ring[j]);
-      __syncthreads();  // every wave is done reading the rows this unit replaces
-#pragma unroll
-      for (int i = 0; i < PF; ++i)
-        if (pf_off[i] >= 0) *reinterpret_cast<u32x4*>(lds + pf_off[i]) = pf[i];
-      const int nv = (Rr.y - Rr.x) * rowvec;
-      // vectors beyond the prefetch (a full ring reload), four loads in flight per thread
-      for (int base = 256 * PF; base < nv; base += 256 * 4) {
-        u32x4 tmp[4];
-        int off[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int idx = base + threadIdx.x + 256 * i;
-          off[i] = -1;
-          if (idx < nv) {
-            const StageAddr sa = stage_addr<BR>(a, Rr.x, U.y, idx, py0, px0, rowvec, nvec, VEC);
-            off[i] = sa.lds;
-            tmp[i] = *reinterpret_cast<const u32x4*>(in + sa.src);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (off[i] >= 0) *reinterpret_cast<u32x4*>(lds + off[i]) = tmp[i];
-      }
+      stage_prefetch<T, RS, PF>(a, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
+      stage_rows<T, RS, PF>(a, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
       __syncthreads();
-      if (u + 1 < u1) stage_prefetch<T, BR, PF>(a, in, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
+      if (u0 + 1 < u1) stage_prefetch<T, RS, PF>(a, in, u0 + 1, py0, px0, rowvec, nvec, pf, pf_off);
+    }
+    for (int u = u0; u < u1; ++u) {
+      const int4 U = a.units[u];
       // LDS base of this lane's positions for the unit's row offset
       const int R = U.x + a.K;
       int lbase[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
-        lbase[t] = (((r + R) % BR) * a.NCOL + c) * a.CS;
+        lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
       }
       if constexpr (sizeof(T) == 4) {
         // FP32: the next bundle's position fragments are read while this bundle's 16 MFMAs
@@ -356,6 +373,21 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
                                 ring[j]);
           }
         }
+      }
+      if (u + 1 < u1) {
+        const int4 Un = a.units[u + 1];
+        const int2 Rn = a.urows[u + 1];
+        // the next unit's first table fragments; their loads overlap the staging below
+#pragma unroll
+        for (int j = 0; j < PD; ++j)
+          load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(Un.z + j, Un.w - 1), g, n,
+                              ring[j]);
+        // one new row right after this unit's rows: its slot is the free one
+        const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
+        if (!free_slot) __syncthreads();  // every wave is done reading the rows replaced
+        stage_rows<T, RS, PF>(a, in, lds, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
+        __syncthreads();  // the next unit's rows are in LDS; every wave is done with this unit
+        if (u + 2 < u1) stage_prefetch<T, RS, PF>(a, in, u + 2, py0, px0, rowvec, nvec, pf, pf_off);
       }
     }
   }

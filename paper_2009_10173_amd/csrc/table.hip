@@ -619,7 +619,7 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   lay.out_len = adjoint ? nz : nt;
   lay.n_tiles = (int)ceil_div(lay.out_len, TM);
   lay.in = pad_geom(g, adjoint ? nt : nz, BR, BC, CH);
-  lay.lds_bytes = (size_t)BR * lay.NCOL * lay.CS * esize;
+  lay.lds_bytes = (size_t)(BR + 1) * lay.NCOL * lay.CS * esize;  // BR rows + one free slot
   const int inner = adjoint ? nt : nz;
   const int nq = (int)ceil_div(inner, G);
   const int qpc = CH / G;  // runs per chunk
