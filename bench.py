@@ -52,18 +52,34 @@ def kernel_times(model, dtype, x, s, reps):
     return out
 
 
+# Sources that decide what the apply kernels do and launch (kernels, layouts, launch plan).
+KERNEL_SOURCES = ("apply.hip", "table.hip", "plan.h", "internal.h")
+
+
+def kernel_code_digest():
+    """SHA-256 of the apply kernels' sources with comments and layout whitespace removed, so
+    that a counter summary stays valid across comment edits and no longer once code changes."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        text = open(os.path.join(ROOT, "paper_2009_10173_amd", "csrc", name)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update((name + "\0" + " ".join(text.split()) + "\0").encode())
+    return h.hexdigest()
+
+
 def profiled_traffic(workload, dtype, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the counters were taken on another workload or the apply kernels have changed since."""
-    import hashlib
+    when the counters were taken on another workload or the kernels' code has changed since."""
     path = os.path.join(ROOT, "profiles", "apply_counters.json")
-    src = os.path.join(ROOT, "paper_2009_10173_amd", "csrc", "apply.hip")
     try:
         prof = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        digest = kernel_code_digest()
     except (OSError, ValueError):
         return None
-    if prof.get("apply_hip_sha256") != sha or prof.get("workload") != workload:
+    if prof.get("kernel_code_digest") != digest or prof.get("workload") != workload:
         return None
     k = prof.get("kernels", {}).get(f"apply {dtype} {kernel}")
     return None if k is None else k["bytes"]

@@ -276,9 +276,10 @@ __device__ __forceinline__ void bundle_mma(const AFrag<T, FP8A, MH>& f, const u3
 // LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 rows) and one patch
 // of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT 16-position
 // tiles.  The tile's bundles are grouped into stage units (chunk, input row offset).  The LDS
-// holds BR input rows (all BC + 2K columns, the chunk's CH inner entries) as a ring indexed by
-// padded row modulo BR: a unit loads only the rows it adds to the ring, and those rows are
-// fetched into registers while the previous unit computes.  Table fragments stream through a
+// holds the BR input rows a unit reads (all BC + 2K columns, the chunk's CH inner entries)
+// plus one free row, as a ring of BR + 1 slots indexed by padded row: a unit loads only the
+// rows it adds to the ring, and those rows are fetched into registers while the previous
+// unit computes.  Table fragments stream through a
 // PD-deep register ring that runs across unit boundaries.  Lane (n = lane % 16,
 // g = lane / 16) holds row n of K-group g of the table and the entries of K-group g for
 // position n.

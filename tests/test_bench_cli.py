@@ -2,7 +2,6 @@
 several GPUs (or a multi-rank launch) ends with a message and exit status 2 before anything
 touches the device; and the HBM traffic it reports is read from the committed counter summary
 only when that summary belongs to the same apply kernels and workload."""
-import hashlib
 import json
 import os
 import subprocess
@@ -35,20 +34,26 @@ def test_traffic_is_taken_only_from_a_matching_profile(tmp_path, monkeypatch):
         sys.path.insert(0, ROOT)
     import bench
     prof = json.load(open(os.path.join(ROOT, "profiles", "apply_counters.json")))
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2009_10173_amd", "csrc", "apply.hip"),
-                              "rb").read()).hexdigest()
     got = bench.profiled_traffic(prof["workload"], "fp32", "adjoint")
-    if prof["apply_hip_sha256"] == sha:
+    if prof["kernel_code_digest"] == bench.kernel_code_digest():
         assert got == prof["kernels"]["apply fp32 adjoint"]["bytes"]
     else:
         assert got is None
     assert bench.profiled_traffic("another_workload", "fp32", "adjoint") is None
-    # a summary taken with other apply kernels is ignored
-    fake = tmp_path / "profiles"
-    fake.mkdir()
-    (fake / "apply_counters.json").write_text(json.dumps(dict(prof, apply_hip_sha256="0" * 64)))
+    # the digest ignores comments and layout but not code
     src = tmp_path / "paper_2009_10173_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "apply.hip").write_bytes(b"// other kernels\n")
+    for name in bench.KERNEL_SOURCES:
+        path = os.path.join(ROOT, "paper_2009_10173_amd", "csrc", name)
+        (src / name).write_text(open(path).read())
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "apply_counters.json").write_text(json.dumps(prof))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base = bench.kernel_code_digest()
+    apply_src = src / "apply.hip"
+    text = apply_src.read_text()
+    apply_src.write_text("// a new comment line\n" + text.replace("\n", "\n\n", 3))
+    assert bench.kernel_code_digest() == base
+    apply_src.write_text(text + "\nstatic int one_more_symbol = 1;\n")
+    assert bench.kernel_code_digest() != base
     assert bench.profiled_traffic(prof["workload"], "fp32", "adjoint") is None
