@@ -96,3 +96,29 @@ def test_imported_asymmetric_table_matches_oracle():
         xg, info = m.solve_lsqr(t64(s.reshape(shp_s)), lam=-1.0, iters=20, inner="fp64")
         assert abs(info["lam"] - lam) <= 1e-12 * lam
         assert rel_l2(xg.cpu().numpy(), x_ref) <= 1e-10
+
+
+def test_repeated_applies_and_solves_hold_device_memory_steady():
+    """Single applies and solves take their temporaries (stage buffers with partial slots,
+    solver vectors) from the library's memory pool, which keeps freed blocks: after a first
+    round, further rounds of the same calls allocate nothing more from the device."""
+    name = "mid"
+    cfg = W.config(name)
+    g = cfg["grid"]
+    x = t32(W.random_image(cfg, 31))
+    y = t32(W.random_signal(cfg, 31))
+    with P.Model(cfg["sensor"], g, dtypes=("fp32", "bf16", "fp8")) as m:
+        def rounds(n):
+            for _ in range(n):
+                for dt in ("fp32", "bf16", "fp8"):
+                    m.forward(x, dt)
+                    m.adjoint(y, dt)
+                m.solve_lsqr(y, lam=-1.0, iters=5, inner="bf16", outer="fp32", refine_sweeps=1)
+                m.solve_l1(y, lam=-1.0, iters=5, inner="fp32")
+            torch.cuda.synchronize()
+        rounds(2)
+        free0 = torch.cuda.mem_get_info()[0]
+        rounds(10)
+        free1 = torch.cuda.mem_get_info()[0]
+    print(f"[memory] free before {free0 / 2**20:.0f} MiB, after {free1 / 2**20:.0f} MiB")
+    assert free0 - free1 <= 16 << 20
