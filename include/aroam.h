@@ -23,6 +23,10 @@
  *     different streams; a model's scratch buffers are per call, so concurrent calls on the
  *     same model are safe.  Destroying a model while work that uses it is in flight is an
  *     error of the caller.
+ *   - Scratch memory of applies and solves (staged inputs, partial sums of cut tiles, solver
+ *     vectors) is allocated stream-ordered from one memory pool per device that the library
+ *     creates on first use.  The pool keeps freed blocks for reuse and holds the peak of
+ *     what was in use until the process ends.
  */
 #ifndef AROAM_H
 #define AROAM_H
