@@ -5,6 +5,7 @@ applies plus the initial A^T, with the fused FP64 vector work).  Prints one JSON
 
 Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16|fp8]
                        [--workload vessels200|vessels400] [--no-cpu-baseline]
+                       [--cpu-detail]
 """
 import argparse
 import json
@@ -132,6 +133,78 @@ def cpu_baseline(cfg, mac_full, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
                         f"{t_table:.1f} s not included"))
 
 
+def cpu_detail(cfg, nnz_full, mac_full, iters, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
+    """The FP64 oracle's table build, A + A^T pair and LSQR reconstruction, each timed with one
+    core and with all cores.  The table with all cores is the full build, timed; every other
+    figure is timed on the depth-slab sample of `cpu_baseline` and scaled to the full workload:
+    the table by the ratio of band entries, the pair by the ratio of algorithmic MACs, and the
+    reconstruction by the MAC ratio and by iteration count from one timed LSQR iteration (the
+    initial A^T and one pair, with its vector work)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import workloads as W
+    from oracle import model as omodel
+    from oracle import operators as oops
+    from oracle import solvers as osolv
+    g = cfg["grid"]
+    ks = [int(f * g["nz"]) for f in depth_fracs]
+    all_cores = min(os.cpu_count() or 1, 16)
+    t0 = time.time()
+    H_full = omodel.build_table(cfg["sensor"], g, workers=all_cores)
+    t_full = time.time() - t0
+    nnz_oracle = int(np.count_nonzero(H_full))
+    del H_full
+    log(f"oracle full table with {all_cores} workers: {t_full:.1f} s")
+    rng = W.rng(99)
+    x = rng.standard_normal((g["ny"], g["nx"], len(ks)))
+    y = rng.standard_normal((g["ny"], g["nx"], g["nt"]))
+    out = {}
+    for label, workers, blas in (("1", 1, 1), ("all", all_cores, None)):
+        t0 = time.time()
+        H = omodel.build_depth_slabs(cfg["sensor"], g, ks, workers=workers)
+        t_table = time.time() - t0
+        nzr = H != 0
+        present = nzr.any(axis=-1)
+        first = np.argmax(nzr, axis=-1)
+        last = g["nt"] - 1 - np.argmax(nzr[..., ::-1], axis=-1)
+        length = np.where(present, last - first + 1, 0)
+        K = g["k_half"]
+        d = np.abs(np.arange(-K, K + 1))
+        pairs = (g["ny"] - d)[:, None] * (g["nx"] - d)[None, :]
+        frac_mac = float(np.sum(pairs[:, :, None] * length)) / mac_full
+        frac_nnz = float(length.sum()) / nnz_full
+        with threadpool_limits(limits=blas):
+            threads = max([p.get("num_threads", 1) for p in threadpool_info()
+                           if p.get("user_api") == "blas"] or [1])
+            t0 = time.time()
+            oops.forward(H, x)
+            oops.adjoint(H, y)
+            t_pair = time.time() - t0
+            t0 = time.time()
+            osolv.lsqr(lambda v: oops.forward(H, v.reshape(x.shape)).ravel(),
+                       lambda v: oops.adjoint(H, v.reshape(y.shape)).ravel(), y, damp=1.0,
+                       iters=1)
+            t_it = time.time() - t0
+        log(f"oracle, {label} core(s): slab table {t_table:.1f} s, pair {t_pair:.1f} s, "
+            f"one LSQR iteration {t_it:.1f} s")
+        out[label] = {"workers": workers, "blas_threads": int(threads),
+                      "table_build_s": t_table / frac_nnz,
+                      "pair_s": t_pair / frac_mac,
+                      "recon_s": t_it * (iters + 0.5) / 1.5 / frac_mac,
+                      "sample_s": {"table": t_table, "pair": t_pair, "lsqr_1_iteration": t_it}}
+    # all cores: the measured full build (a slab sample has fewer slabs than workers)
+    out["all"]["table_build_s"] = t_full
+    out["table_band_entries"] = {"oracle": nnz_oracle, "model": int(nnz_full)}
+    out["sample"] = (f"depth slabs {ks} of the full {g['nx']}x{g['ny']} scan "
+                     f"({100 * frac_mac:.2f}% of the algorithmic MACs, {100 * frac_nnz:.2f}% of "
+                     f"the table's band entries); the all-core table time is the full build, "
+                     f"the others are scaled from the sample (table by band entries, pair by "
+                     f"MACs, reconstruction of {iters} LSQR iterations from one iteration by "
+                     f"MACs and iteration count)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +214,9 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-detail", action="store_true",
+                    help="also time the oracle's table build, pair and reconstruction with one "
+                         "core and with all cores (about two more minutes)")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the serving leg (0 skips it)")
     args = ap.parse_args()
@@ -280,6 +356,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(cfg, info["mac_alg"])
+    if args.cpu_detail:
+        log("timing the CPU oracle's table, pair and reconstruction on one and all cores")
+        result["cpu_detail"] = cpu_detail(cfg, info["nnz"], info["mac_alg"], iters)
     if model is not None:
         model.close()
     print(json.dumps(result), flush=True)
