@@ -138,8 +138,8 @@ def cpu_detail(cfg, nnz_full, mac_full, iters, depth_fracs=(0.31, 0.32, 0.67, 0.
     core and with all cores.  The table with all cores is the full build, timed; every other
     figure is timed on the depth-slab sample of `cpu_baseline` and scaled to the full workload:
     the table by the ratio of band entries, the pair by the ratio of algorithmic MACs, and the
-    reconstruction by the MAC ratio and by iteration count from one timed LSQR iteration (the
-    initial A^T and one pair, with its vector work)."""
+    reconstruction by the MAC ratio from the initial A^T and `iters` times one iteration (one
+    timed LSQR iteration with its set-up, less the initial A^T)."""
     import numpy as np
     from threadpoolctl import threadpool_info, threadpool_limits
 
@@ -179,20 +179,26 @@ def cpu_detail(cfg, nnz_full, mac_full, iters, depth_fracs=(0.31, 0.32, 0.67, 0.
                            if p.get("user_api") == "blas"] or [1])
             t0 = time.time()
             oops.forward(H, x)
+            t_fwd = time.time() - t0
+            t0 = time.time()
             oops.adjoint(H, y)
-            t_pair = time.time() - t0
+            t_adj = time.time() - t0
+            t_pair = t_fwd + t_adj
             t0 = time.time()
             osolv.lsqr(lambda v: oops.forward(H, v.reshape(x.shape)).ravel(),
                        lambda v: oops.adjoint(H, v.reshape(y.shape)).ravel(), y, damp=1.0,
                        iters=1)
             t_it = time.time() - t0
-        log(f"oracle, {label} core(s): slab table {t_table:.1f} s, pair {t_pair:.1f} s, "
-            f"one LSQR iteration {t_it:.1f} s")
+        log(f"oracle, {label} core(s): slab table {t_table:.1f} s, forward {t_fwd:.1f} s, "
+            f"adjoint {t_adj:.1f} s, LSQR set-up and one iteration {t_it:.1f} s")
+        # LSQR = one A^T to start, then per iteration one pair and the vector work
+        recon = t_adj + iters * (t_it - t_adj)
         out[label] = {"workers": workers, "blas_threads": int(threads),
                       "table_build_s": t_table / frac_nnz,
                       "pair_s": t_pair / frac_mac,
-                      "recon_s": t_it * (iters + 0.5) / 1.5 / frac_mac,
-                      "sample_s": {"table": t_table, "pair": t_pair, "lsqr_1_iteration": t_it}}
+                      "recon_s": recon / frac_mac,
+                      "sample_s": {"table": t_table, "forward": t_fwd, "adjoint": t_adj,
+                                   "lsqr_1_iteration": t_it}}
     # all cores: the measured full build (a slab sample has fewer slabs than workers)
     out["all"]["table_build_s"] = t_full
     out["table_band_entries"] = {"oracle": nnz_oracle, "model": int(nnz_full)}
@@ -200,8 +206,8 @@ def cpu_detail(cfg, nnz_full, mac_full, iters, depth_fracs=(0.31, 0.32, 0.67, 0.
                      f"({100 * frac_mac:.2f}% of the algorithmic MACs, {100 * frac_nnz:.2f}% of "
                      f"the table's band entries); the all-core table time is the full build, "
                      f"the others are scaled from the sample (table by band entries, pair by "
-                     f"MACs, reconstruction of {iters} LSQR iterations from one iteration by "
-                     f"MACs and iteration count)")
+                     f"MACs, reconstruction of {iters} LSQR iterations as the initial A^T plus "
+                     f"{iters} times one timed iteration, by MACs)")
     return out
 
 
