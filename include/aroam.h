@@ -235,8 +235,9 @@ typedef struct {
 /* Tikhonov / least squares (Eq. 5-6): min ||s - A x||^2 + lambda ||x||^2 by LSQR (Paige and
  * Saunders) with damp = sqrt(lambda); lambda = 0 gives plain least squares.  x receives the
  * result (device, image layout).  All norms, dot products and the LSQR scalar recurrences are
- * FP64 on the device.  Allocates its work vectors from the device heap for the duration of
- * the call.  info (host) may be NULL.
+ * FP64 on the device.  Takes its work vectors from the per-device memory pool (see
+ * Conventions) for the duration of the call; aroam_solve_footprint gives their size.  info
+ * (host) may be NULL.
  * Errors: AROAM_EINVAL, AROAM_EUNSUPPORTED, AROAM_ENOMEM, AROAM_EDEVICE, AROAM_ENONFINITE. */
 int aroam_solve_lsqr(const aroam_model* model, const aroam_solve_opts* opts, const void* s,
                      void* x, aroam_solve_info* info, void* stream);
