@@ -206,7 +206,8 @@ int aroam_adjoint(const aroam_model* model, int dtype, const void* s, void* x, v
  *   lambda        Eq. 5 weight; < 0 selects the default rule computed on the device
  *                 (Tikhonov: 1e-2 ||A^T s||_2; L1: 5e-3 max|A^T s|) and reports it in info
  *   iters         iterations (fixed count, x0 = 0, no early stop)
- *   refine_sweeps LSQR: residual-correction sweeps after the first solve (0 = none)
+ *   refine_sweeps LSQR: residual-correction sweeps after the first solve (0 = none); sweeps
+ *                 need lambda > 0, also when the rule computes it (AROAM_EINVAL otherwise)
  *   anchor_period FISTA with inner != outer: after the warm-up, a high-precision anchor
  *                 gradient every this many iterations (0 = 5)
  *   anchor_warmup FISTA with inner != outer: the first this many iterations take the
@@ -248,10 +249,12 @@ int aroam_solve_lsqr(const aroam_model* model, const aroam_solve_opts* opts, con
 int aroam_solve_l1(const aroam_model* model, const aroam_solve_opts* opts, const void* s,
                    void* x, aroam_solve_info* info, void* stream);
 
-/* Ragged batch of applies for serving: n independent applies, request i using models[i],
- * dtype, x[i] and s[i] (device pointers of FP32 vectors), issued as one launch per
- * operator class.  Each request's result equals that of aroam_forward / aroam_adjoint on it
- * alone, bit for bit.  Errors as aroam_forward. */
+/* Ragged batch of applies: n independent applies, request i using models[i], dtype, x[i]
+ * and s[i] (device pointers of FP32 vectors), enqueued on the stream in index order, each
+ * with the launches aroam_forward / aroam_adjoint would make for it, so each result equals
+ * the single apply's bit for bit.  n = 0 does nothing and succeeds.  A NULL model is
+ * rejected before anything is enqueued; any other error of entry i is returned after
+ * entries 0 .. i-1 have been enqueued.  Errors as aroam_forward. */
 int aroam_forward_batch(int n, const aroam_model* const* models, int dtype,
                         const float* const* x, float* const* s, void* stream);
 int aroam_adjoint_batch(int n, const aroam_model* const* models, int dtype,
