@@ -57,3 +57,38 @@ def test_traffic_is_taken_only_from_a_matching_profile(tmp_path, monkeypatch):
     apply_src.write_text(text + "\nstatic int one_more_symbol = 1;\n")
     assert bench.kernel_code_digest() != base
     assert bench.profiled_traffic(prof["workload"], "fp32", "adjoint") is None
+
+
+def test_cpu_detail_scales_its_sample_to_the_whole_workload():
+    """The oracle timing leg on the 16x16 case: the band entries it counts on the full table
+    equal the count it is given, and every figure is scaled from a sample that is a fraction
+    of the workload (so the scaled time is at least the sample's)."""
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import numpy as np
+
+    import bench
+    import workloads as W
+    from oracle import model as omodel
+    cfg = W.config("tiny")
+    g = cfg["grid"]
+    H = omodel.build_table(cfg["sensor"], g)
+    nzr = H != 0
+    present = nzr.any(axis=-1)
+    first = np.argmax(nzr, axis=-1)
+    last = g["nt"] - 1 - np.argmax(nzr[..., ::-1], axis=-1)
+    length = np.where(present, last - first + 1, 0)
+    K = g["k_half"]
+    d = np.abs(np.arange(-K, K + 1))
+    pairs = (g["ny"] - d)[:, None] * (g["nx"] - d)[None, :]
+    nnz, mac = int(length.sum()), int(np.sum(pairs[:, :, None] * length))
+    out = bench.cpu_detail(cfg, nnz, mac, iters=3)
+    assert out["table_band_entries"] == {"oracle": nnz, "model": nnz}
+    assert out["1"]["blas_threads"] == 1 and out["1"]["workers"] == 1
+    for label in ("1", "all"):
+        r = out[label]
+        smp = r["sample_s"]
+        assert r["pair_s"] >= smp["forward"] + smp["adjoint"] > 0
+        assert r["recon_s"] > 0
+    assert out["1"]["table_build_s"] >= out["1"]["sample_s"]["table"]
+    assert "depth slabs" in out["sample"]
