@@ -86,11 +86,26 @@ def profiled_traffic(workload, dtype, kernel):
     return None if k is None else k["bytes"]
 
 
+def _sample_work(H, g):
+    """Band entries and algorithmic MACs of a depth-slab table H[dy, dx, slab, n]: per column
+    the window from its first to its last nonzero sample, times the scan positions that see
+    the column's offset."""
+    import numpy as np
+    nzr = H != 0
+    present = nzr.any(axis=-1)
+    first = np.argmax(nzr, axis=-1)
+    last = g["nt"] - 1 - np.argmax(nzr[..., ::-1], axis=-1)
+    length = np.where(present, last - first + 1, 0)
+    K = g["k_half"]
+    d = np.abs(np.arange(-K, K + 1))
+    pairs = (g["ny"] - d)[:, None] * (g["nx"] - d)[None, :]
+    return int(length.sum()), int(np.sum(pairs[:, :, None] * length))
+
+
 def cpu_baseline(cfg, mac_full, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
     """The FP64 oracle's A + A^T pair on a bounded sample of the same workload: the full scan
     grid and footprint restricted to a few depth slabs (at the given fractions of the depth
     range), scaled to full-workload pairs/s by the ratio of algorithmic MACs."""
-    import numpy as np
     from threadpoolctl import threadpool_info
 
     import workloads as W
@@ -102,15 +117,7 @@ def cpu_baseline(cfg, mac_full, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
     H = omodel.build_depth_slabs(cfg["sensor"], g, ks)
     t_table = time.time() - t0
     log(f"oracle table for depth slabs {ks}: {t_table:.1f} s")
-    nzr = H != 0                                  # [dy, dx, slab, n]
-    present = nzr.any(axis=-1)
-    first = np.argmax(nzr, axis=-1)
-    last = g["nt"] - 1 - np.argmax(nzr[..., ::-1], axis=-1)
-    length = np.where(present, last - first + 1, 0)
-    K = g["k_half"]
-    d = np.abs(np.arange(-K, K + 1))
-    pairs = (g["ny"] - d)[:, None] * (g["nx"] - d)[None, :]
-    mac_sample = int(np.sum(pairs[:, :, None] * length))
+    _, mac_sample = _sample_work(H, g)
     rng = W.rng(99)
     x = rng.standard_normal((g["ny"], g["nx"], len(ks)))
     y = rng.standard_normal((g["ny"], g["nx"], g["nt"]))
@@ -164,16 +171,9 @@ def cpu_detail(cfg, nnz_full, mac_full, iters, depth_fracs=(0.31, 0.32, 0.67, 0.
         t0 = time.time()
         H = omodel.build_depth_slabs(cfg["sensor"], g, ks, workers=workers)
         t_table = time.time() - t0
-        nzr = H != 0
-        present = nzr.any(axis=-1)
-        first = np.argmax(nzr, axis=-1)
-        last = g["nt"] - 1 - np.argmax(nzr[..., ::-1], axis=-1)
-        length = np.where(present, last - first + 1, 0)
-        K = g["k_half"]
-        d = np.abs(np.arange(-K, K + 1))
-        pairs = (g["ny"] - d)[:, None] * (g["nx"] - d)[None, :]
-        frac_mac = float(np.sum(pairs[:, :, None] * length)) / mac_full
-        frac_nnz = float(length.sum()) / nnz_full
+        nnz_sample, mac_sample = _sample_work(H, g)
+        frac_mac = mac_sample / mac_full
+        frac_nnz = nnz_sample / nnz_full
         with threadpool_limits(limits=blas):
             threads = max([p.get("num_threads", 1) for p in threadpool_info()
                            if p.get("user_api") == "blas"] or [1])
