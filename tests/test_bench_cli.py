@@ -92,3 +92,18 @@ def test_cpu_detail_scales_its_sample_to_the_whole_workload():
         assert r["recon_s"] > 0
     assert out["1"]["table_build_s"] >= out["1"]["sample_s"]["table"]
     assert "depth slabs" in out["sample"]
+
+
+def test_cpu_baseline_reports_the_oracle_rate_on_its_sample():
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    from oracle import model as omodel
+    cfg = W.config("tiny")
+    g = cfg["grid"]
+    _, mac = bench._sample_work(omodel.build_table(cfg["sensor"], g), g)
+    out = bench.cpu_baseline(cfg, mac)
+    assert out["kind"] == "oracle" and out["unit"] == "A+A^T pairs/s"
+    assert out["value"] > 0 and out["cores"] >= 1
+    assert "depth slabs" in out["sample"]
