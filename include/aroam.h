@@ -50,6 +50,11 @@ typedef enum {
 
 typedef enum { AROAM_FP64 = 0, AROAM_FP32 = 1, AROAM_BF16 = 2, AROAM_FP8E4M3 = 3 } aroam_dtype;
 
+/* Largest lateral model extent k_half (offsets -k_half .. k_half).  The staged applies keep,
+ * per workgroup, 9 scan rows x (32 + 2 k_half) columns x 80 bytes of input in the 160 KiB LDS
+ * of a compute unit.  At the 5 um step this is about 0.97 mm of lateral extent. */
+#define AROAM_MAX_K_HALF 97
+
 /* Spherical-cap sensor (Methods, "Forward modeling", Eq. 3; "AR-OAM set-up").
  *   radius_m   radius of curvature = focal distance
  *   aperture_m chord diameter of the cap (numerical aperture = aperture / (2 radius))
@@ -69,7 +74,8 @@ typedef struct {
  *   nx, ny, step_m scan positions (== voxel columns) and their lateral spacing
  *   nz, dz_m       voxel depths z_k = (k - nz/2) dz from the focal plane, + = away from sensor
  *   nt             time samples per scan position; sample nt/2 is the focal arrival R / c
- *   k_half         lateral model extent: offsets -k_half..k_half in x and y
+ *   k_half         lateral model extent: offsets -k_half..k_half in x and y,
+ *                  0 <= k_half <= AROAM_MAX_K_HALF
  *   footprint_mode 0: full (2 k_half + 1)^2 square at every depth;
  *                  1: also (dx^2 + dy^2) step^2 <= (rho0 + |z| tan(theta_max))^2 with
  *                     rho0 = 2 * 0.71 lambda(f0) / NA (the diffraction-limit rule, Results)
@@ -130,7 +136,7 @@ typedef struct {
  * and stored, and the offsets of a class share it.
  * On success *out owns the device tables; release with aroam_model_destroy.
  * Errors: AROAM_EINVAL for NULL pointers or sizes out of range (nx, ny, nz, nt >= 1,
- * 0 <= k_half <= 256, at most 4096 sub-elements), AROAM_ENOMEM, AROAM_EDEVICE.
+ * 0 <= k_half <= AROAM_MAX_K_HALF, at most 4096 sub-elements), AROAM_ENOMEM, AROAM_EDEVICE.
  * Synchronises `stream` before returning. */
 int aroam_build_model(const aroam_sensor* sensor, const aroam_grid* grid, unsigned dtype_mask,
                       void* stream, aroam_model** out);
@@ -238,23 +244,35 @@ typedef struct {
  * result (device, image layout).  All norms, dot products and the LSQR scalar recurrences are
  * FP64 on the device.  Takes its work vectors from the per-device memory pool (see
  * Conventions) for the duration of the call; aroam_solve_footprint gives their size.  info
- * (host) may be NULL.
+ * (host) may be NULL; on every return it holds the status, and iters_done the iterations
+ * completed (0 when the set-up failed).
+ * Non-finite values: a non-finite norm (from a NaN or infinity in s, or one that arises)
+ * stops the solve with AROAM_ENONFINITE and info->iters_done = the iterations completed
+ * before it, counted over all sweeps; the lambda rule of a refined solve on such an s gives
+ * AROAM_ENONFINITE with iters_done = 0.  x is then undefined.
  * Errors: AROAM_EINVAL, AROAM_EUNSUPPORTED, AROAM_ENOMEM, AROAM_EDEVICE, AROAM_ENONFINITE. */
 int aroam_solve_lsqr(const aroam_model* model, const aroam_solve_opts* opts, const void* s,
                      void* x, aroam_solve_info* info, void* stream);
 
 /* L1 (Eq. 5, 7): min ||s - A x||^2 + lambda ||x||_1 by FISTA (Beck and Teboulle) with step
  * 1 / L, L = 2.02 sigma_max(A)^2 from the power method unless opts->lipschitz > 0, and the
- * soft threshold lambda / L.  Same conventions and errors as aroam_solve_lsqr. */
+ * soft threshold lambda / L.  Same conventions and errors as aroam_solve_lsqr.  Non-finite
+ * values: a non-finite L, lambda (the rule's max|A^T s| carries a NaN through), power-method
+ * norm, or gradient step y - g / L (tested before the soft threshold, which would map a NaN
+ * to 0) stops the solve with AROAM_ENONFINITE; info->iters_done = the FISTA iterations
+ * completed before it (0 when it happened in the power method or the parameters). */
 int aroam_solve_l1(const aroam_model* model, const aroam_solve_opts* opts, const void* s,
                    void* x, aroam_solve_info* info, void* stream);
 
 /* Ragged batch of applies: n independent applies, request i using models[i], dtype, x[i]
  * and s[i] (device pointers of FP32 vectors), enqueued on the stream in index order, each
  * with the launches aroam_forward / aroam_adjoint would make for it, so each result equals
- * the single apply's bit for bit.  n = 0 does nothing and succeeds.  A NULL model is
- * rejected before anything is enqueued; any other error of entry i is returned after
- * entries 0 .. i-1 have been enqueued.  Errors as aroam_forward. */
+ * the single apply's bit for bit.  dtype is AROAM_FP32, AROAM_BF16 or AROAM_FP8E4M3 (the
+ * vectors are FP32; AROAM_FP64 is rejected, also when n = 0).  n = 0 with a valid dtype does
+ * nothing and succeeds.  A NULL model or a bad dtype is rejected with AROAM_EINVAL before
+ * anything is enqueued; any other error
+ * of entry i is returned after entries 0 .. i-1 have been enqueued.  Errors as
+ * aroam_forward. */
 int aroam_forward_batch(int n, const aroam_model* const* models, int dtype,
                         const float* const* x, float* const* s, void* stream);
 int aroam_adjoint_batch(int n, const aroam_model* const* models, int dtype,

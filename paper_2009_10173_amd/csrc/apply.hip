@@ -527,10 +527,10 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
   const unsigned long long bit = 1ull << (dev & 63);
   if (!(attr_set.load() & bit)) {
     AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024));
+                                  (int)kLdsBytes));
     attr_set.fetch_or(bit);
   }
-  AROAM_CHECK(lay.lds_bytes <= 160 * 1024, AROAM_EINVAL,
+  AROAM_CHECK(lay.lds_bytes <= kLdsBytes, AROAM_EINVAL,
               "lateral footprint too wide for the LDS stage (%zu bytes)", lay.lds_bytes);
   StagedArgs a;
   a.pieces = lay.d_pieces;
@@ -567,17 +567,14 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
 
 }  // namespace
 
-int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* stage,
-          hipStream_t st) {
-  AROAM_CHECK(dtype >= AROAM_FP64 && dtype <= AROAM_FP8E4M3, AROAM_EINVAL, "bad dtype %d", dtype);
-  AROAM_CHECK(in && out, AROAM_EINVAL, "NULL vector");
-  AROAM_CHECK((m.dtype_mask >> dtype) & 1u, AROAM_EUNSUPPORTED,
-              "model was not packed for dtype %d", dtype);
+namespace {
+
+// The launches of one apply into the stage buffer `buf` (stage_bytes() bytes).
+int launch_apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* buf,
+                 hipStream_t st) {
   const Layout& lay = layout_for(m, adjoint, dtype);
   const Pack& pk = adjoint ? m.adj_pack[dtype] : m.fwd_pack[dtype];
   const PadGeom& pg = lay.in;
-  void* buf = stage;
-  if (!buf) AROAM_TRY(pool_alloc(&buf, stage_bytes(m, adjoint, dtype), st));
   const dim3 sgrid((unsigned)(pg.nyp * pg.nxp));
   if (dtype == AROAM_FP64)
     hipLaunchKernelGGL((k_stage<double, double>), sgrid, dim3(256), 0, st, (const double*)in,
@@ -605,13 +602,37 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
       AROAM_TRY((launch_staged<uint16_t, true, kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
   }
   AROAM_HIP(hipGetLastError());
-  if (!stage) AROAM_HIP(hipFreeAsync(buf, st));
+  return AROAM_OK;
+}
+
+}  // namespace
+
+int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* stage,
+          hipStream_t st) {
+  AROAM_CHECK(dtype >= AROAM_FP64 && dtype <= AROAM_FP8E4M3, AROAM_EINVAL, "bad dtype %d", dtype);
+  AROAM_CHECK(in && out, AROAM_EINVAL, "NULL vector");
+  AROAM_CHECK((m.dtype_mask >> dtype) & 1u, AROAM_EUNSUPPORTED,
+              "model was not packed for dtype %d", dtype);
+  const Layout& lay = layout_for(m, adjoint, dtype);
+  AROAM_CHECK(!lay.staged || lay.lds_bytes <= kLdsBytes, AROAM_EINVAL,
+              "lateral footprint too wide for the LDS stage (%zu bytes)", lay.lds_bytes);
+  if (stage) return launch_apply(m, adjoint, dtype, in, out, stage, st);
+  // a stage buffer of its own from the pool, returned to the pool on every path
+  void* buf = nullptr;
+  AROAM_TRY(pool_alloc(&buf, stage_bytes(m, adjoint, dtype), st));
+  const int rc = launch_apply(m, adjoint, dtype, in, out, buf, st);
+  const hipError_t e = hipFreeAsync(buf, st);
+  if (rc != AROAM_OK) return rc;
+  AROAM_CHECK(e == hipSuccess, AROAM_EDEVICE, "hipFreeAsync failed: %s", hipGetErrorString(e));
   return AROAM_OK;
 }
 
 int apply_batch(int n, const Model* const* ms, bool adjoint, int dtype, const float* const* in,
                 float* const* out, hipStream_t st) {
   AROAM_CHECK(n >= 0 && (n == 0 || (ms && in && out)), AROAM_EINVAL, "bad batch arguments");
+  // the batch's vectors are FP32: FP64 applies would read and write doubles
+  AROAM_CHECK(dtype == AROAM_FP32 || dtype == AROAM_BF16 || dtype == AROAM_FP8E4M3, AROAM_EINVAL,
+              "batched applies take FP32, BF16 or FP8 (dtype %d)", dtype);
   for (int i = 0; i < n; ++i) {
     AROAM_CHECK(ms[i], AROAM_EINVAL, "NULL model in batch");
     AROAM_TRY(apply(*ms[i], adjoint, dtype, in[i], out[i], nullptr, st));

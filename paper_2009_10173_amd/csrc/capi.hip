@@ -241,6 +241,11 @@ int aroam_solve_l1(const aroam_model* model, const aroam_solve_opts* opts, const
 static int batch(int n, const aroam_model* const* models, bool adjoint, int dtype,
                  const float* const* in, float* const* out, void* stream) {
   aroam::clear_error();
+  // the batch's vectors are FP32, so FP64 (double vectors) is not a batch dtype
+  if (dtype != AROAM_FP32 && dtype != AROAM_BF16 && dtype != AROAM_FP8E4M3) {
+    aroam::set_error("batched applies take FP32, BF16 or FP8 (dtype %d)", dtype);
+    return AROAM_EINVAL;
+  }
   if (n < 0 || (n > 0 && (!models || !in || !out))) {
     aroam::set_error("bad batch arguments");
     return AROAM_EINVAL;

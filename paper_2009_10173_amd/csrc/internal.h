@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "aroam.h"
+#include "staging.h"
 
 namespace aroam {
 
@@ -49,9 +50,8 @@ int pool_alloc(void** p, size_t bytes, hipStream_t st);
 constexpr int kTile = 16;     // output rows per tile (time samples or depths) = MFMA M
 constexpr int kLaneGroups = 4; // K-groups per bundle = 64-lane wave / 16
 constexpr int kTileRows8 = 32;  // output rows per tile of the G = 8 (BF16 / FP8) layouts
-constexpr int kPatchRows = 8;   // scan rows per workgroup patch of the staged kernels
-constexpr int kPatchCols = 32;  // scan columns per workgroup patch (two 16-position tiles)
 constexpr int kMaxElements = 4096;  // two FP64 values per sub-element fit in 64 KiB of LDS
+static_assert(max_k_half() == AROAM_MAX_K_HALF, "the header's k_half limit is the LDS stage's");
 
 // ------------------------------------------------------------------------------------------
 // Padded operand geometry.  Inputs of an apply are staged into a zero-padded buffer
@@ -177,7 +177,8 @@ size_t stage_bytes(const Model& m, bool adjoint, int dtype);
 // stage_bytes() bytes that the call may overwrite.
 int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* stage,
           hipStream_t st);
-// Ragged batch: one launch per kernel class covering all requests.
+// Ragged batch of FP32-vector applies (dtype FP32, BF16 or FP8): the single applies of the
+// requests, enqueued in index order on one stream.
 int apply_batch(int n, const Model* const* ms, bool adjoint, int dtype, const float* const* in,
                 float* const* out, hipStream_t st);
 

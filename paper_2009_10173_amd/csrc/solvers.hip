@@ -36,11 +36,15 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
+// Maximum that carries a NaN through (fmax drops it), so that a NaN in a vector reaches the
+// scalar derived from its maximum and is detected there.
+__device__ inline double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+
 __device__ inline double block_max(double v, double* sh) {
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = nan_max(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }
   const double r = sh[0];
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(kRedThreads) void k_amax_partial(const T* __restric
   double acc = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride)
-    acc = fmax(acc, fabs((double)a[i]));
+    acc = nan_max(acc, fabs((double)a[i]));
   const double s = block_max(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict_
   __shared__ double sh[kRedThreads];
   double acc = 0.0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x)
-    acc = is_max ? fmax(acc, part0[i]) : acc + part0[i];
+    acc = is_max ? nan_max(acc, part0[i]) : acc + part0[i];
   double r = is_max ? block_max(acc, sh) : block_sum(acc, sh);
   if (part1) {
     double acc1 = 0.0;
@@ -292,7 +296,8 @@ __global__ void k_scale_dev(T* __restrict__ y, const T* __restrict__ a, const do
 
 struct FistaDev {
   double L, lambda, rq, ww, vv, inv, amax;
-  int bad;
+  int bad;       // a non-finite value was met (sticky: later kernels do nothing)
+  int bad_iter;  // FISTA iterations completed before it (0 in the power method / parameters)
 };
 
 __global__ void k_fista_reset(FistaDev* f) {
@@ -305,7 +310,7 @@ __global__ void k_power_scalars(FistaDev* f) {
   f->rq = f->vv;
   const double nw = sqrt(f->ww);
   f->inv = nw > 0 ? 1.0 / nw : 0.0;
-  if (!isfinite(nw)) f->bad = 1;
+  if (!isfinite(nw) || !isfinite(f->vv)) f->bad = 1;
 }
 
 __global__ void k_power_start(FistaDev* f) {
@@ -321,26 +326,34 @@ __global__ void k_fista_params(FistaDev* f, double lipschitz, double lambda, int
   if (!(f->L > 0) || !isfinite(f->L) || !isfinite(f->lambda)) f->bad = 1;
 }
 
-// One FISTA update: g = ga + 2 t2 (either may be absent), x+ = S_{lambda/L}(y - g / L),
-// y = x+ + mom (x+ - x), x = x+.
+// One FISTA update (iteration `it`, counted from 0): g = ga + 2 t2 (either may be absent),
+// x+ = S_{lambda/L}(y - g / L), y = x+ + mom (x+ - x), x = x+.  The soft threshold maps a NaN
+// to 0, so the step's argument is tested before it: a non-finite gradient step marks the
+// solve as failed after `it` iterations (every thread that sees one stores the same values).
 template <typename T>
 __global__ __launch_bounds__(256) void k_fista_step(T* __restrict__ y, T* __restrict__ x,
                                                     const T* __restrict__ ga,
                                                     const T* __restrict__ t2, double mom,
-                                                    long long n, const FistaDev* __restrict__ f) {
+                                                    long long n, int it, FistaDev* f) {
   if (f->bad) return;
   const double L = f->L, thr = f->lambda / L;
   const long long stride = (long long)gridDim.x * blockDim.x;
+  bool finite = true;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
     double g = 0.0;
     if (ga) g += (double)ga[i];
     if (t2) g += 2.0 * (double)t2[i];
     const double v = (double)y[i] - g / L;
+    finite = finite && isfinite(v);
     const double av = fabs(v) - thr;
     const double xn = av > 0 ? copysign(av, v) : 0.0;
     const double xo = (double)x[i];
     x[i] = (T)xn;
     y[i] = (T)(xn + mom * (xn - xo));
+  }
+  if (!finite) {
+    f->bad_iter = it;
+    f->bad = 1;
   }
 }
 
@@ -527,6 +540,8 @@ class SolverT final : public Solver {
       double red = 0.0;
       AROAM_HIP(hipMemcpyAsync(&red, &d_->red, sizeof(red), hipMemcpyDeviceToHost, stream));
       AROAM_HIP(hipStreamSynchronize(stream));
+      AROAM_CHECK(std::isfinite(red), AROAM_ENONFINITE,
+                  "non-finite value in A^T s (lambda rule of the refined LSQR)");
       lam_ = 1e-2 * std::sqrt(red);
       rule = 0;
     }
@@ -675,7 +690,7 @@ class SolverT final : public Solver {
       hipLaunchKernelGGL(k_axpby<T>, dim3(gs), dim3(256), 0, stream, ts_, (const T*)ts_, s_, 1.0, -1.0, ns_);
       AROAM_TRY(adj(o_.inner, ts_, tx_));
       hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, stream, y_, xp_,
-                         (const T*)nullptr, (const T*)tx_, mom, nx_, (const FistaDev*)f_);
+                         (const T*)nullptr, (const T*)tx_, mom, nx_, it, f_);
     } else if (it < warmup_ || (it - warmup_) % period_ == 0) {
       // anchor: the exact gradient at y in the outer precision
       AROAM_HIP(hipMemcpyAsync(xa_, y_, nx_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
@@ -685,7 +700,7 @@ class SolverT final : public Solver {
       hipLaunchKernelGGL(k_axpby<T>, dim3(gx), dim3(256), 0, stream, ga_, (const T*)tx_,
                          (const T*)nullptr, 2.0, 0.0, nx_);
       hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, stream, y_, xp_, (const T*)ga_,
-                         (const T*)nullptr, mom, nx_, (const FistaDev*)f_);
+                         (const T*)nullptr, mom, nx_, it, f_);
     } else {
       // correction: g = g_a + 2 A^T A (y - x_a) with the inner-precision applies
       hipLaunchKernelGGL(k_axpby<T>, dim3(gx), dim3(256), 0, stream, dv_, (const T*)y_,
@@ -693,7 +708,7 @@ class SolverT final : public Solver {
       AROAM_TRY(fwd(o_.inner, dv_, ts_));
       AROAM_TRY(adj(o_.inner, ts_, tx_));
       hipLaunchKernelGGL(k_fista_step<T>, dim3(gx), dim3(256), 0, stream, y_, xp_, (const T*)ga_,
-                         (const T*)tx_, mom, nx_, (const FistaDev*)f_);
+                         (const T*)tx_, mom, nx_, it, f_);
     }
     AROAM_HIP(hipGetLastError());
     t_ = tn;
@@ -720,7 +735,7 @@ class SolverT final : public Solver {
     AROAM_HIP(hipMemcpyAsync(&h, f_, sizeof(h), hipMemcpyDeviceToHost, stream));
     AROAM_HIP(hipStreamSynchronize(stream));
     if (info) {
-      info->iters_done = h.bad ? 0 : (int)std::max<long long>(0, enqueued_ - npow_);
+      info->iters_done = h.bad ? h.bad_iter : (int)std::max<long long>(0, enqueued_ - npow_);
       info->status = h.bad ? AROAM_ENONFINITE : AROAM_OK;
       info->lambda = h.lambda;
       info->lipschitz = h.L;
@@ -729,7 +744,7 @@ class SolverT final : public Solver {
       info->beta = 0.0;
     }
     if (h.bad) {
-      set_error("non-finite value in FISTA (Lipschitz constant or lambda)");
+      set_error("non-finite value in FISTA after %d iterations", h.bad_iter);
       return AROAM_ENONFINITE;
     }
     return AROAM_OK;
@@ -753,7 +768,14 @@ int make_solver(const Model& m, int kind, const aroam_solve_opts& o, const void*
 int run_blocking(const Model& m, int kind, const aroam_solve_opts& o, const void* s, void* x,
                  aroam_solve_info* info, hipStream_t st) {
   Solver* sv = nullptr;
-  AROAM_TRY(solver_create(m, kind, o, s, x, st, &sv));
+  const int rc0 = solver_create(m, kind, o, s, x, st, &sv);
+  if (rc0 != AROAM_OK) {
+    if (info) {  // failed in the set-up: no iteration was done
+      *info = aroam_solve_info{};
+      info->status = rc0;
+    }
+    return rc0;
+  }
   int rc = sv->step(0x7fffffff);
   if (rc == AROAM_OK) rc = sv->finish(info);
   else (void)hipStreamSynchronize(st);

@@ -443,7 +443,7 @@ int build_layout(const Model& m, bool adjoint, int G, Layout& lay, size_t& bytes
 // groups.  Lane (n, g) of a bundle reads vector run_g of staged column c + n + col_g; with a
 // column stride of 80 bytes (5 groups of 16 bytes) its bank group is 5 (c + n + col_g) + run_g
 // (mod 16).  The patch offset c and the row start shift all lanes of a read alike.
-constexpr int kColumnGroups = 5;  // LDS column stride in 16-byte groups (CH * esize + 16)
+constexpr int kColumnGroups = kColumnBytes / 16;  // LDS column stride in 16-byte groups
 
 bool pair_conflict_free(int col_a, int run_a, int col_b, int run_b) {
   static const int lo_hi[8] = {0, 1, 2, 3, 12, 13, 14, 15};
@@ -613,13 +613,15 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   lay.BR = BR;
   lay.BC = BC;
   lay.NCOL = BC + 2 * K;
-  AROAM_CHECK(CH * esize == 64 && G * esize == 16, AROAM_EINVAL,
+  AROAM_CHECK(CH * esize == kChunkBytes && G * esize == 16, AROAM_EINVAL,
               "staged layout needs 64-byte chunks of four 16-byte runs");
-  lay.CS = kColumnGroups * 16 / esize;  // 64 bytes of chunk + 16 bytes of padding
+  lay.CS = kColumnBytes / esize;  // 64 bytes of chunk + 16 bytes of padding
   lay.out_len = adjoint ? nz : nt;
   lay.n_tiles = (int)ceil_div(lay.out_len, TM);
   lay.in = pad_geom(g, adjoint ? nt : nz, BR, BC, CH);
   lay.lds_bytes = (size_t)(BR + 1) * lay.NCOL * lay.CS * esize;  // BR rows + one free slot
+  AROAM_CHECK(BR == kPatchRows && BC == kPatchCols && (long long)lay.lds_bytes == staged_lds_bytes(K),
+              AROAM_EINVAL, "staged layout shape differs from the LDS stage's");
   const int inner = adjoint ? nt : nz;
   const int nq = (int)ceil_div(inner, G);
   const int qpc = CH / G;  // runs per chunk
@@ -1119,7 +1121,9 @@ int check_grid(const aroam_grid* g) {
   AROAM_CHECK(g->nx >= 1 && g->ny >= 1 && g->nz >= 1 && g->nt >= 1 && g->nx <= 65536 &&
                   g->ny <= 65536 && g->nz <= 65536 && g->nt <= 65536,
               AROAM_EINVAL, "grid sizes out of range");
-  AROAM_CHECK(g->k_half >= 0 && g->k_half <= 256, AROAM_EINVAL, "k_half out of range");
+  AROAM_CHECK(g->k_half >= 0 && g->k_half <= AROAM_MAX_K_HALF, AROAM_EINVAL,
+              "k_half %d out of range 0..%d (the staged applies' LDS row ring holds %d + 2 k_half "
+              "columns)", g->k_half, AROAM_MAX_K_HALF, kPatchCols);
   return AROAM_OK;
 }
 

@@ -138,3 +138,45 @@ def test_build_rejects_bad_discretisation_without_gpu():
         assert lib.aroam_build_model(ctypes.byref(sen), ctypes.byref(g), 0, None,
                                      ctypes.byref(h)) == -1
         assert not h.value
+
+
+def test_batch_rejects_fp64_without_gpu():
+    """The batch's vectors are FP32, so an FP64 batch (which would read and write doubles) is
+    rejected before anything is looked at or enqueued, for any n; FP32 with n = 0 succeeds."""
+    lib = P.load_library()
+    for fn in (lib.aroam_forward_batch, lib.aroam_adjoint_batch):
+        assert fn(0, None, P.AROAM_FP64, None, None, None) == -1
+        assert "FP32, BF16 or FP8" in P.aroam_last_error()
+        assert fn(0, None, 7, None, None, None) == -1
+        assert fn(0, None, P.AROAM_FP32, None, None, None) == 0
+
+
+def test_k_half_limit_is_the_lds_stage_limit(tmp_path):
+    """The largest k_half the header allows is the largest whose staged row ring (9 rows x
+    (32 + 2 k_half) columns x 80 bytes) fits the 160 KiB LDS of a compute unit; the build
+    rejects one more before any device call."""
+    src = tmp_path / "k.cc"
+    src.write_text('#include <cstdio>\n#include "aroam.h"\n#include "staging.h"\n'
+                   "int main() { std::printf(\"%d %d %lld %lld %lld\\n\", AROAM_MAX_K_HALF, "
+                   "aroam::max_k_half(), aroam::staged_lds_bytes(AROAM_MAX_K_HALF), "
+                   "aroam::staged_lds_bytes(AROAM_MAX_K_HALF + 1), aroam::kLdsBytes); }\n")
+    exe = tmp_path / "k"
+    subprocess.run(["g++", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I",
+                    os.path.join(ROOT, "paper_2009_10173_amd", "csrc"), str(src), "-o", str(exe)],
+                   check=True)
+    kmax, kcalc, lds, lds_next, cap = map(int, subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.split())
+    assert kmax == kcalc
+    assert cap == 160 * 1024
+    assert lds == 9 * (32 + 2 * kmax) * 80 <= cap < lds_next
+    import workloads as W
+    lib = P.load_library()
+    cfg = W.config("tiny")
+    sen = P.binding._sensor(cfg["sensor"])
+    h = ctypes.c_void_p()
+    g = P.binding._grid(dict(cfg["grid"], k_half=kmax + 1))
+    assert lib.aroam_build_model(ctypes.byref(sen), ctypes.byref(g), 0, None, ctypes.byref(h)) == -1
+    assert "k_half" in P.aroam_last_error() and not h.value
+    H = __import__("numpy").zeros(1)
+    assert lib.aroam_import_model(ctypes.byref(g), H.ctypes.data_as(ctypes.c_void_p), None, None,
+                                  0, None, ctypes.byref(h)) == -1

@@ -302,6 +302,75 @@ def test_nonfinite_signal_is_reported():
     assert e.value.status == -4
 
 
+def _raw_solve(fn_name, m, s, **opts):
+    """One solve through the C entry point itself, returning (status, info) without raising,
+    so that the info of a failed solve can be read."""
+    import ctypes
+    lib = P.load_library()
+    inner = P.DTYPES[opts.pop("inner", "fp32")]
+    outer = P.DTYPES[opts.pop("outer")] if "outer" in opts else inner
+    x = torch.empty(m.image_shape, dtype=torch.float64 if inner == P.AROAM_FP64 else torch.float32,
+                    device=s.device)
+    o = P.binding._opts(inner=inner, outer=outer, **opts)
+    info = P.binding.SolveInfo()
+    info.iters_done, info.status = -123, -123
+    rc = getattr(lib, fn_name)(m.handle, ctypes.byref(o), ctypes.c_void_p(s.data_ptr()),
+                               ctypes.c_void_p(x.data_ptr()), ctypes.byref(info),
+                               P.binding._stream(None))
+    return rc, info
+
+
+def _nan_signal(cfg, seed=3):
+    s = W.random_signal(cfg, seed)
+    s[3, 4, 10] = np.nan
+    return s
+
+
+@pytest.mark.parametrize("how", ["explicit", "rule"])
+def test_nonfinite_signal_stops_fista(how):
+    """A NaN in s stops FISTA with AROAM_ENONFINITE: with explicit lambda and L at the first
+    gradient step (the soft threshold would map the NaN to 0, so the step is tested before it);
+    with the lambda rule in the parameters, since max|A^T s| carries the NaN through."""
+    cfg = W.config("tiny")
+    m = gpu_model("tiny")
+    s = t32(_nan_signal(cfg))
+    if how == "explicit":
+        rc, info = _raw_solve("aroam_solve_l1", m, s, lam=1e-3, lipschitz=1.0, iters=5)
+    else:
+        rc, info = _raw_solve("aroam_solve_l1", m, s, lam=-1.0, iters=5, power_iters=5)
+    assert rc == -4 and info.status == -4
+    assert info.iters_done == 0
+    assert "non-finite" in P.aroam_last_error()
+
+
+def test_fista_divergence_reports_iterations_done():
+    """A step 1 / L far too long (L = 1e-45 with lambda = 0) keeps the first FISTA step finite
+    in FP64 but beyond the FP32 range, so the image holds infinities; the next gradient step is
+    non-finite and the solve stops after exactly one completed iteration."""
+    cfg = W.config("tiny")
+    m = gpu_model("tiny")
+    s = t32(W.random_signal(cfg, 3))
+    rc, info = _raw_solve("aroam_solve_l1", m, s, lam=0.0, lipschitz=1e-45, iters=6)
+    assert rc == -4 and info.status == -4
+    assert info.iters_done == 1
+
+
+@pytest.mark.parametrize("inner", ["bf16", "fp32"])
+def test_nonfinite_signal_stops_refined_lsqr(inner):
+    """Refined LSQR with the lambda rule computes lambda from A^T s before the solve; a NaN in s
+    makes it non-finite, which is AROAM_ENONFINITE (not an argument error) with no iteration
+    done.  Plain LSQR stops at its first norm with iters_done = 0."""
+    cfg = W.config("tiny")
+    m = gpu_model("tiny")
+    s = t32(_nan_signal(cfg))
+    rc, info = _raw_solve("aroam_solve_lsqr", m, s, lam=-1.0, iters=5, inner=inner,
+                          outer="fp32", refine_sweeps=2)
+    assert rc == -4 and info.status == -4 and info.iters_done == 0
+    assert "non-finite" in P.aroam_last_error()
+    rc, info = _raw_solve("aroam_solve_lsqr", m, s, lam=0.0, iters=5)
+    assert rc == -4 and info.status == -4 and info.iters_done == 0
+
+
 def test_unpacked_dtype_is_rejected():
     cfg = W.config("tiny")
     m = gpu_model("tiny", ("fp32",))
