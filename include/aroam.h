@@ -198,6 +198,23 @@ int aroam_model_query(const aroam_model* model, aroam_model_info* info);
  * Synchronous.  Errors: AROAM_EINVAL (model NULL), AROAM_EDEVICE. */
 int aroam_model_export_table(const aroam_model* model, double* dense, int* col_lo, int* col_hi);
 
+/* Copy the reduced-precision table of one apply direction to HOST memory, in the layout of
+ * aroam_model_export_table, each entry being exactly the value that the dtype's apply
+ * multiplies (for error analysis of the quantised table):
+ *   dtype    AROAM_FP32: the FP64 table rounded to FP32;  AROAM_BF16: those FP32 values
+ *            rounded to BF16 (nearest, ties to even);  AROAM_FP8E4M3: e4m3(v / scale) * scale
+ *            with the FP32 value v / scale rounded to the nearest e4m3 code (ties to even) and
+ *            scale the smallest power of two >= amax / 448 of the entry's (offset, 16-depth
+ *            block), amax the largest |value| of the FP64 table in that block
+ *   adjoint  0: the forward pack, 1: the adjoint pack (each is checked on its own)
+ *   dense    [(2 k_half + 1)][(2 k_half + 1)][nz][nt] doubles, H[dy + K][dx + K][k][n]; required
+ *   block_scales  FP8 only, may be NULL: [(2 k_half + 1)][(2 k_half + 1)][ceil(nz / 16)] floats,
+ *            the scale of each (offset, 16-depth block), 0 where the block has no entries
+ * Synchronous.  Errors: AROAM_EINVAL (NULL model or dense, dtype not FP32 / BF16 / FP8),
+ * AROAM_EUNSUPPORTED (dtype not packed), AROAM_EDEVICE. */
+int aroam_model_export_quantized(const aroam_model* model, int dtype, int adjoint, double* dense,
+                                 float* block_scales);
+
 /* s = A x  (Eq. 4 with the translational symmetry of the Methods):
  *   s[iy, ix, n] = sum_{o, (iy+dy, ix+dx) in grid} sum_k H[o][n, k] x[iy+dy, ix+dx, k].
  * Every element of s is written (no accumulation into s).  x and s must not overlap.

@@ -75,6 +75,8 @@ _SYMBOLS = {
                             C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "aroam_model_query": ([C.c_void_p, C.POINTER(ModelInfo)], C.c_int),
     "aroam_model_export_table": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "aroam_model_export_quantized": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p],
+                                     C.c_int),
     "aroam_forward": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "aroam_adjoint": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "aroam_solve_lsqr": ([C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
@@ -238,6 +240,21 @@ def aroam_model_export_table(h, grid, dense=True):
     return H, lo, hi
 
 
+def aroam_model_export_quantized(h, grid, dtype, adjoint=False):
+    """Returns (H [2K+1][2K+1][nz][nt] float64 of the values the dtype's apply multiplies,
+    block scales [2K+1][2K+1][ceil(nz/16)] float32 for FP8 else None)."""
+    import numpy as np
+    K, nz, nt = grid["k_half"], grid["nz"], grid["nt"]
+    W = 2 * K + 1
+    dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    H = np.empty((W, W, nz, nt), dtype=np.float64)
+    sc = np.empty((W, W, (nz + 15) // 16), dtype=np.float32) if dtype == AROAM_FP8E4M3 else None
+    _check(load_library().aroam_model_export_quantized(
+        h, dtype, int(bool(adjoint)), H.ctypes.data_as(C.c_void_p),
+        None if sc is None else sc.ctypes.data_as(C.c_void_p)))
+    return H, sc
+
+
 def aroam_forward(h, dtype, x, s, stream=None):
     _check(load_library().aroam_forward(h, dtype, _ptr(x), _ptr(s), _stream(stream)))
 
@@ -370,6 +387,9 @@ class Model:
 
     def export_table(self, dense=True):
         return aroam_model_export_table(self.handle, self.grid, dense)
+
+    def export_quantized(self, dtype, adjoint=False):
+        return aroam_model_export_quantized(self.handle, self.grid, dtype, adjoint)
 
     @property
     def image_shape(self):

@@ -200,6 +200,16 @@ int aroam_model_export_table(const aroam_model* model, double* dense, int* col_l
   return AROAM_OK;
 }
 
+int aroam_model_export_quantized(const aroam_model* model, int dtype, int adjoint, double* dense,
+                                 float* block_scales) {
+  aroam::clear_error();
+  if (!model) {
+    aroam::set_error("NULL model");
+    return AROAM_EINVAL;
+  }
+  return aroam::export_quantized(*model->m, dtype, adjoint != 0, dense, block_scales);
+}
+
 int aroam_forward(const aroam_model* model, int dtype, const void* x, void* s, void* stream) {
   aroam::clear_error();
   if (!model) {

@@ -168,6 +168,9 @@ int import_model(const aroam_grid* g, const double* dense, const int* col_lo,
 int build_model(const aroam_sensor* s, const aroam_grid* g, const aroam_filter* f,
                 unsigned mask, hipStream_t st, Model** out);
 void destroy_model(Model* m);
+// Host copy of the FP32 / BF16 / FP8 pack of one direction in the dense table layout, each
+// entry the value that the dtype's apply multiplies (FP8: also the block scales).
+int export_quantized(const Model& m, int dtype, bool adjoint, double* dense, float* scales);
 
 // apply.hip
 const Layout& layout_for(const Model& m, bool adjoint, int dtype);

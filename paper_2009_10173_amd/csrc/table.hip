@@ -1115,6 +1115,82 @@ int build_model(const aroam_sensor* s, const aroam_grid* g, const aroam_filter* 
   return finish_model(m, rc, mask, st, out);
 }
 
+namespace {
+
+// Value of an OCP e4m3 code (sign, 4 exponent bits of bias 7, 3 mantissa bits; exponent 0 is
+// subnormal; 0x7f / 0xff are NaN).
+double e4m3_value(uint8_t c) {
+  const int e = (c >> 3) & 15, mant = c & 7;
+  if (e == 15 && mant == 7) return std::nan("");
+  const double mag = e == 0 ? std::ldexp(mant / 8.0, -6) : std::ldexp(1.0 + mant / 8.0, e - 7);
+  return (c & 0x80) ? -mag : mag;
+}
+
+template <typename T>
+int download(std::vector<T>& h, const void* d, size_t n) {
+  h.resize(std::max<size_t>(1, n));
+  if (n > 0 && hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("download of a packed table failed");
+    return AROAM_EDEVICE;
+  }
+  return AROAM_OK;
+}
+
+}  // namespace
+
+int export_quantized(const Model& m, int dtype, bool adjoint, double* dense, float* scales) {
+  AROAM_CHECK(dense, AROAM_EINVAL, "NULL output");
+  AROAM_CHECK(dtype == AROAM_FP32 || dtype == AROAM_BF16 || dtype == AROAM_FP8E4M3, AROAM_EINVAL,
+              "export of the FP32, BF16 or FP8 packs (dtype %d)", dtype);
+  AROAM_CHECK((m.dtype_mask >> dtype) & 1u, AROAM_EUNSUPPORTED, "model was not packed for dtype %d",
+              dtype);
+  const Layout& lay = layout_for(m, adjoint, dtype);
+  const Pack& pk = adjoint ? m.adj_pack[dtype] : m.fwd_pack[dtype];
+  const int nz = m.grid.nz, nt = m.grid.nt, TM = lay.TM, G = lay.G, NH = TM / kTile;
+  const int nblk = (int)ceil_div(nz, 16);
+  const size_t n_groups = (size_t)lay.n_bundles * kLaneGroups;
+  std::vector<int4> groups;
+  AROAM_TRY(download(groups, lay.d_groups, n_groups));
+  const size_t esize = dtype == AROAM_FP32 ? 4 : dtype == AROAM_BF16 ? 2 : 1;
+  std::vector<uint8_t> raw;
+  AROAM_TRY(download(raw, pk.d, n_groups * TM * G * esize));
+  std::vector<float> gscale;
+  if (dtype == AROAM_FP8E4M3) AROAM_TRY(download(gscale, pk.d_scale, n_groups * NH));
+  std::fill(dense, dense + (size_t)m.n_off * nz * nt, 0.0);
+  if (scales) std::fill(scales, scales + (size_t)m.n_off * nblk, 0.0f);
+  for (size_t q = 0; q < n_groups; ++q) {
+    const int4 gd = groups[q];  // (offset index, run start, tile, active)
+    if (gd.x < 0) continue;
+    for (int r = 0; r < TM; ++r)
+      for (int j = 0; j < G; ++j) {
+        const int n = adjoint ? gd.y + j : TM * gd.z + r;
+        const int k = adjoint ? TM * gd.z + r : gd.y + j;
+        if (n >= nt || k >= nz) continue;
+        const size_t e = q * TM * G + (size_t)r * G + j;
+        double v;
+        if (dtype == AROAM_FP32) {
+          float f;
+          std::memcpy(&f, &raw[4 * e], 4);
+          v = f;
+        } else if (dtype == AROAM_BF16) {
+          const uint32_t bits = (uint32_t)(raw[2 * e] | (raw[2 * e + 1] << 8)) << 16;
+          float f;
+          std::memcpy(&f, &bits, 4);
+          v = f;
+        } else {
+          // a lane's entries of both halves are adjacent: [group][row in half][half][G]
+          const int h = r / kTile;
+          const size_t pos = q * TM * G + (size_t)((r % kTile) * NH + h) * G + j;
+          const float sc = gscale[q * NH + h];
+          v = e4m3_value(raw[pos]) * (double)sc;
+          if (scales) scales[(size_t)gd.x * nblk + k / 16] = sc;
+        }
+        dense[((size_t)gd.x * nz + k) * nt + n] = v;
+      }
+  }
+  return AROAM_OK;
+}
+
 int check_grid(const aroam_grid* g) {
   AROAM_CHECK(g->c_mps > 0 && g->fs_hz > 0 && g->step_m > 0 && g->dz_m > 0, AROAM_EINVAL,
               "invalid grid spacing");
