@@ -1,11 +1,18 @@
-"""Benchmark of the AR-OAM hot path on one MI355X: LSQR-Tikhonov reconstructions of the
-200x200-position workload (voxels 200x200x128 at 10 um, Nt 512, cone footprint up to 41x41
-offsets, 50 iterations).  One step = one full reconstruction (50 iterations = 50 A + 50 A^T
-applies plus the initial A^T, with the fused FP64 vector work).  Prints one JSON line.
+"""Benchmark of the AR-OAM hot path on one MI355X.
+
+Headline workload: the 400x400-position scan at 5 um (voxels 400x400x256 at 5 um, Nt 1024,
+cone footprint up to 81x81 offsets), FP32 applies.  One step = one LSQR-Tikhonov iteration:
+one A and one A^T apply with the fused FP64 vector work.  The timed region is one solve of
+exactly `--steps` iterations (its set-up adds the initial A^T u, half a pair); `value` is A+A^T
+pairs per second, (steps + 0.5) / elapsed.  Beside it, in the same JSON line: the full
+50-iteration FP32 reconstruction, the FP8- and BF16-refined reconstructions (2 sweeps) with
+their difference to it, the 200x200 workload as a secondary leg, the serving leg (a Poisson
+trace over the whole request mix), the roofline of the dominant kernel, and the CPU oracle on
+a bounded sample.  Prints one JSON line.
 
 Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16|fp8]
-                       [--workload vessels200|vessels400] [--no-cpu-baseline]
-                       [--cpu-detail]
+                       [--workload vessels400|vessels200] [--secondary vessels200|none]
+                       [--serve-requests N] [--no-cpu-baseline] [--cpu-detail]
 """
 import argparse
 import json
@@ -102,10 +109,11 @@ def _sample_work(H, g):
     return int(length.sum()), int(np.sum(pairs[:, :, None] * length))
 
 
-def cpu_baseline(cfg, mac_full, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
-    """The FP64 oracle's A + A^T pair on a bounded sample of the same workload: the full scan
-    grid and footprint restricted to a few depth slabs (at the given fractions of the depth
-    range), scaled to full-workload pairs/s by the ratio of algorithmic MACs."""
+def cpu_baseline(cfg, mac_full, depth_fracs=(0.31, 0.32, 0.67, 0.68), side=None):
+    """The FP64 oracle's A + A^T pair on a bounded sample of the same workload: the footprint
+    and time axis of the full problem restricted to a few depth slabs (at the given fractions
+    of the depth range) and, with `side`, to a side x side scan; scaled to full-workload
+    pairs/s by the ratio of algorithmic MACs."""
     from threadpoolctl import threadpool_info
 
     import workloads as W
@@ -114,30 +122,29 @@ def cpu_baseline(cfg, mac_full, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
     g = cfg["grid"]
     ks = [int(f * g["nz"]) for f in depth_fracs]
     t0 = time.time()
-    H = omodel.build_depth_slabs(cfg["sensor"], g, ks)
+    H = omodel.build_depth_slabs(cfg["sensor"], g, ks, workers=min(os.cpu_count() or 1, 16))
     t_table = time.time() - t0
     log(f"oracle table for depth slabs {ks}: {t_table:.1f} s")
-    _, mac_sample = _sample_work(H, g)
+    gs = dict(g) if side is None else dict(g, nx=side, ny=side)
+    _, mac_sample = _sample_work(H, gs)
     rng = W.rng(99)
-    x = rng.standard_normal((g["ny"], g["nx"], len(ks)))
-    y = rng.standard_normal((g["ny"], g["nx"], g["nt"]))
-    times = []
-    for _ in range(2):
-        t0 = time.time()
-        oops.forward(H, x)
-        oops.adjoint(H, y)
-        times.append(time.time() - t0)
-        log(f"oracle A+A^T pair on the sample: {times[-1]:.1f} s")
-    t_pair = min(times)
+    x = rng.standard_normal((gs["ny"], gs["nx"], len(ks)))
+    y = rng.standard_normal((gs["ny"], gs["nx"], g["nt"]))
+    t0 = time.time()
+    oops.forward(H, x)
+    oops.adjoint(H, y)
+    t_pair = time.time() - t0
+    log(f"oracle A+A^T pair on the sample: {t_pair:.1f} s")
     threads = max([d.get("num_threads", 1) for d in threadpool_info()
                    if d.get("user_api") == "blas"] or [1])
     frac = mac_sample / mac_full
+    scan = f"{gs['nx']}x{gs['ny']} scan" + ("" if side is None else
+                                               f" (of the {g['nx']}x{g['ny']} workload)")
     return dict(value=frac / t_pair, unit="A+A^T pairs/s", cores=int(threads), kind="oracle",
-                sample=(f"FP64 oracle A+A^T pair on depth slabs {ks} of the full "
-                        f"{g['nx']}x{g['ny']} scan "
-                        f"({100 * frac:.2f}% of the algorithmic MACs), {t_pair:.2f} s per sample "
-                        f"pair, scaled by the MAC ratio; table build for the slabs "
-                        f"{t_table:.1f} s not included"))
+                sample=(f"FP64 oracle A+A^T pair on depth slabs {ks} of a {scan} with the "
+                        f"workload's footprint and time axis ({100 * frac:.3f}% of the "
+                        f"algorithmic MACs), {t_pair:.2f} s per sample pair, scaled by the MAC "
+                        f"ratio; table build for the slabs {t_table:.1f} s not included"))
 
 
 def cpu_detail(cfg, nnz_full, mac_full, iters, depth_fracs=(0.31, 0.32, 0.67, 0.68)):
@@ -211,21 +218,81 @@ def cpu_detail(cfg, nnz_full, mac_full, iters, depth_fracs=(0.31, 0.32, 0.67, 0.
     return out
 
 
+def roofline(info, dtype, kt, workload):
+    """Roofline of the dominant (slower) apply kernel from its event-timed average launch."""
+    import paper_2009_10173_amd as P
+    dom = max(kt, key=kt.get)
+    di = P.DTYPES[dtype]
+    mac_exec = info["mac_exec"][di] if dom == "forward" else info["mac_exec_adj"][di]
+    achieved = 2.0 * info["mac_alg"] / (kt[dom] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    return {"bound": "mfma",
+            "kernel": (f"{dom} (e4m3 table, bf16 MFMA)" if dtype == "fp8" else
+                       f"{dom} ({dtype} MFMA)"),
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "issued_frac": 2.0 * mac_exec / (kt[dom] * 1e-3) / 1e12 / ISSUE_PEAK[dtype],
+            "kernel_ms": kt[dom],
+            "traffic": profiled_traffic(workload, dtype, dom)}
+
+
+def signals(model, cfg, dev):
+    """Seeded phantom -> FP32 forward -> peak-SNR Gaussian noise, all resident in HBM."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    x0 = torch.from_numpy(W.make_phantom(cfg, 0).astype(np.float32)).to(dev)
+    clean = model.forward(x0, "fp32")
+    sigma = clean.abs().max().item() * 10 ** (-cfg["snr_db"] / 20)
+    s = clean + sigma * torch.from_numpy(W.unit_noise(cfg, 0).astype(np.float32)).to(dev)
+    torch.cuda.synchronize()
+    return x0, s
+
+
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def secondary_leg(name, dev, reps=3):
+    """Plain FP32 LSQR reconstructions of another workload: pairs/s and kernel times."""
+    import paper_2009_10173_amd as P
+    import workloads as W
+    cfg = W.config(name)
+    iters = cfg["solver"]["iters"]
+    with P.Model(cfg["sensor"], cfg["grid"], dtypes=("fp32",)) as model:
+        info = model.info()
+        x0, s = signals(model, cfg, dev)
+        model.solve_lsqr(s, lam=-1.0, iters=iters)
+        lat = [timed(lambda: model.solve_lsqr(s, lam=-1.0, iters=iters))[1] for _ in range(reps)]
+        kt = kernel_times(model, "fp32", x0, s, 10)
+    t = sorted(lat)[len(lat) // 2]
+    return {"workload": name, "iters": iters, "recon_ms": t * 1e3,
+            "pairs_per_s": (iters + 0.5) / t,
+            "tmac_s": 2.0 * info["mac_alg"] * (iters + 0.5) / t / 1e12,
+            "kernel_ms": kt, "roofline": roofline(info, "fp32", kt, name)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="vessels200")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="vessels400")
+    ap.add_argument("--secondary", default="vessels200")
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-detail", action="store_true",
                     help="in the CPU baseline, also time the oracle's table build, pair and "
-                         "reconstruction with one core and with all cores (about two more "
-                         "minutes)")
-    ap.add_argument("--serve-requests", type=int, default=12,
+                         "reconstruction with one core and with all cores (minutes more)")
+    ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests in the serving leg (0 skips it)")
+    ap.add_argument("--serve-modes", default="fifo_fp32,served_bf16r")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -233,7 +300,6 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2009_10173_amd as P
@@ -244,49 +310,25 @@ def main():
     g = cfg["grid"]
     iters = cfg["solver"]["iters"]
     log(f"building model {args.workload}")
-    torch.cuda.synchronize()
-    t0 = time.time()
-    # inner precisions of the refined legs: BF16 and FP8 for the FP32 bench, else its own
-    lows = ["bf16", "fp8"] if args.dtype == "fp32" else [args.dtype]
-    model = P.Model(cfg["sensor"], g, dtypes=tuple(sorted({"fp32", args.dtype, *lows})))
-    torch.cuda.synchronize()
-    t_build = time.time() - t0
+    lows = ["fp8", "bf16"] if args.dtype == "fp32" else [args.dtype]
+    dtypes = tuple(sorted({"fp32", args.dtype, *lows}))
+    (model, t_build) = timed(lambda: P.Model(cfg["sensor"], g, dtypes=dtypes))
     info = model.info()
     log(f"model built in {t_build:.2f} s: nnz {info['nnz']}, MAC_alg {info['mac_alg']:.3e}")
+    x0, s = signals(model, cfg, dev)
 
-    x0 = torch.from_numpy(W.make_phantom(cfg, 0).astype(np.float32)).to(dev)
-    clean = model.forward(x0, "fp32")
-    sigma = clean.abs().max().item() * 10 ** (-cfg["snr_db"] / 20)
-    s = clean + sigma * torch.from_numpy(W.unit_noise(cfg, 0).astype(np.float32)).to(dev)
-    torch.cuda.synchronize()
-
-    def step():
-        return model.solve_lsqr(s, lam=-1.0, iters=iters, inner=args.dtype)
-
-    for i in range(args.warmup):
-        step()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    lat = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        t1 = time.perf_counter()
-        x, sinfo = step()
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t1)
-        log(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
-    elapsed = time.perf_counter() - t_start
-    pairs_per_step = iters + 0.5          # 50 A + 50 A^T + the initial A^T
-    pairs_s = args.steps * pairs_per_step / elapsed
+    # headline: LSQR iterations, `warmup` untimed, then one solve of exactly `steps`
+    if args.warmup > 0:
+        timed(lambda: model.solve_lsqr(s, lam=-1.0, iters=args.warmup, inner=args.dtype))
+        log(f"warmup: {args.warmup} LSQR iterations done")
+    (xk, sinfo), elapsed = timed(lambda: model.solve_lsqr(s, lam=-1.0, iters=args.steps,
+                                                          inner=args.dtype))
+    log(f"timed: {args.steps} LSQR iterations in {elapsed:.2f} s")
+    pairs_s = (args.steps + 0.5) / elapsed
 
     kt = kernel_times(model, args.dtype, x0, s, args.kernel_reps)
-    dom = max(kt, key=kt.get)
+    log(f"kernel times {args.dtype}: {kt}")
     di = P.DTYPES[args.dtype]
-    mac_exec = info["mac_exec"][di] if dom == "forward" else info["mac_exec_adj"][di]
-    flops = 2.0 * info["mac_alg"]
-    achieved = flops / (kt[dom] * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.dtype]
-    mfma_issued = 2.0 * mac_exec / (kt[dom] * 1e-3) / 1e12 / ISSUE_PEAK[args.dtype]
     result = {
         "metric": METRIC,
         "value": pairs_s,
@@ -300,75 +342,75 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE_TAG[args.dtype],
         "data": "synthetic",
-        "config": {"workload": (f"{args.workload}: LSQR-Tikhonov {iters} its, scan "
-                                f"{g['nx']}x{g['ny']} at {g['step_m'] * 1e6:g} um, voxels "
-                                f"{g['nx']}x{g['ny']}x{g['nz']}, Nt {g['nt']}, cone footprint "
+        "config": {"workload": (f"{args.workload}: scan {g['nx']}x{g['ny']} at "
+                                f"{g['step_m'] * 1e6:g} um, voxels {g['nx']}x{g['ny']}x{g['nz']} "
+                                f"at {g['dz_m'] * 1e6:g} um, Nt {g['nt']}, cone footprint "
                                 f"K={g['k_half']}, {cfg['phantom']['n']} curved-tube phantom, "
-                                f"{cfg['snr_db']:g} dB"),
-                   "solver": "lsqr", "iters": iters},
+                                f"{cfg['snr_db']:g} dB; step = one LSQR-Tikhonov iteration "
+                                f"(A + A^T + FP64 vector work)"),
+                   "solver": "lsqr", "step": "lsqr_iteration"},
         "tmac_s": 2.0 * info["mac_alg"] * pairs_s / 1e12,
-        "recon_ms_p50": float(np.percentile(lat, 50) * 1e3),
-        "recon_ms_p99": float(np.percentile(lat, 99) * 1e3),
         "kernel_ms": kt,
         "fill": {"forward": info["mac_alg"] / info["mac_exec"][di],
                  "adjoint": info["mac_alg"] / info["mac_exec_adj"][di]},
+        "mac_alg": info["mac_alg"],
         "table_build_s": t_build,
-        # workgroup rows of each staged launch: output row tiles, and pieces where the launch
-        # plan cuts heavy tiles
         "launch": {dt: {"forward": {"tiles": info["row_tiles"][P.DTYPES[dt]],
                                     "pieces": info["pieces"][P.DTYPES[dt]]},
                         "adjoint": {"tiles": info["row_tiles_adj"][P.DTYPES[dt]],
                                     "pieces": info["pieces_adj"][P.DTYPES[dt]]}}
-                   for dt in sorted({"fp32", args.dtype, *lows})},
+                   for dt in dtypes},
         "lambda": sinfo["lam"],
-        "roofline": {"bound": "mfma", "kernel": (f"{dom} (e4m3 table, bf16 MFMA)" if args.dtype == "fp8"
-                                else f"{dom} ({args.dtype} MFMA)"),
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "issued_frac": mfma_issued,
-                     "traffic": profiled_traffic(args.workload, args.dtype, dom)},
+        "roofline": roofline(info, args.dtype, kt, args.workload),
     }
-    # reduced precision with refinement on the same workload: BF16 / FP8 applies, FP32
-    # residuals, two sweeps
-    x32 = x if args.dtype == "fp32" else model.solve_lsqr(s, lam=-1.0, iters=iters)[0]
+    # the full reconstruction in the plain precision, then reduced precision with two FP32
+    # residual-correction sweeps
+    (x32, _), t_rec = timed(lambda: model.solve_lsqr(s, lam=-1.0, iters=iters, inner=args.dtype))
+    log(f"{args.dtype} reconstruction ({iters} iterations): {t_rec:.2f} s")
+    result["recon"] = {"iters": iters, "dtype": args.dtype, "recon_ms": t_rec * 1e3,
+                       "pairs_per_s": (iters + 0.5) / t_rec}
     for lo in lows:
-        log(f"{lo}-refined reconstruction (2 sweeps)")
-        model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32", refine_sweeps=2)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        xr, rinfo = model.solve_lsqr(s, lam=-1.0, iters=iters, inner=lo, outer="fp32",
-                                     refine_sweeps=2)
-        torch.cuda.synchronize()
-        t_ref = time.perf_counter() - t1
-        diff = ((xr - x32).norm() / x32.norm()).item()
+        if lo == args.dtype:
+            continue
         kt_lo = kernel_times(model, lo, x0, s, args.kernel_reps)
+        (xr, rinfo), t_ref = timed(lambda: model.solve_lsqr(
+            s, lam=-1.0, iters=iters, inner=lo, outer=args.dtype, refine_sweeps=2))
+        diff = ((xr - x32).norm() / x32.norm()).item()
+        log(f"{lo}-refined reconstruction (2 sweeps): {t_ref:.2f} s, diff {diff:.2e}")
         li = P.DTYPES[lo]
         result[f"{lo}_refined"] = {
             "recon_ms": t_ref * 1e3, "sweeps": 2,
+            "speedup_vs_plain": t_rec / t_ref,
             "pairs_per_s": ((iters + 0.5) * 3 + 2 + 0.5) / t_ref,
-            "rel_diff_vs_fp32_recon": diff,
+            "rel_diff_vs_plain_recon": diff,
             "kernel_ms": kt_lo,
-            f"issued_frac_{lo}": {k: 2.0 * (info["mac_exec"][li] if k == "forward" else
-                                            info["mac_exec_adj"][li]) / (v * 1e-3) / 1e12
-                                  / ISSUE_PEAK[lo] for k, v in kt_lo.items()},
+            "roofline": roofline(info, lo, kt_lo, args.workload),
+            "issued_frac": {k: 2.0 * (info["mac_exec"][li] if k == "forward" else
+                                      info["mac_exec_adj"][li]) / (v * 1e-3) / 1e12
+                            / ISSUE_PEAK[lo] for k, v in kt_lo.items()},
         }
+    model.close()
+    del x0, s, xk, x32
+    torch.cuda.empty_cache()
+    if args.secondary != "none":
+        log(f"secondary leg: {args.secondary}")
+        result["secondary"] = secondary_leg(args.secondary, dev)
+        log(f"secondary: {result['secondary']['pairs_per_s']:.1f} pairs/s")
     if args.serve_requests > 0:
         log(f"serving leg: {args.serve_requests} mixed requests")
-        model.close()
-        model = None
         from paper_2009_10173_amd import serve as S
-        res = S.main(["--requests", str(args.serve_requests), "--sides", "64,96,128,192",
-                      "--nz", "64,128"], quiet=True)
-        result["serving"] = {k: res[k] for k in ("rate_per_s", "fifo_fp32", "served_fp32",
-                                                  "served_bf16r")}
+        res = S.main(["--requests", str(args.serve_requests), "--calibrate", "predict",
+                      "--modes", args.serve_modes, "--budget-gb", "8"], quiet=True)
+        result["serving"] = res
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(cfg, info["mac_alg"])
+        side = 96 if g["nx"] > 200 else None
+        fracs = (0.31, 0.68) if side else (0.31, 0.32, 0.67, 0.68)
+        result["cpu_baseline"] = cpu_baseline(cfg, info["mac_alg"], fracs, side)
         if args.cpu_detail:
             log("timing the CPU oracle's table, pair and reconstruction on one and all cores")
             result["cpu_baseline"]["detail"] = cpu_detail(cfg, info["nnz"], info["mac_alg"],
                                                           iters)
-    if model is not None:
-        model.close()
     print(json.dumps(result), flush=True)
 
 

@@ -109,20 +109,32 @@ struct LsqrDev {
   double lambda;
   double nrm_u2, nrm_v2, red;
   int done, bad, bad_iter, iter;
-  int failed;  // sticky across the solves of a refinement schedule: an earlier solve failed
+  int failed;      // sticky across the solves of a refinement schedule: an earlier solve failed
+  int base;        // iterations of the schedule completed before this solve started
+  int fail_iters;  // iterations of the schedule completed before the failure (sticky)
 };
 
 __device__ inline bool stop(const LsqrDev* d) { return d->done || d->bad || d->failed; }
 
-// Start a new LSQR solve in the state block; `first` clears the sticky failure flag.
-__global__ void k_lsqr_reset(LsqrDev* d, double damp, double gamma, int first) {
+// A non-finite value met after `iter` iterations of the current solve.
+__device__ inline void lsqr_fail(LsqrDev* d, int iter) {
+  d->bad = 1;
+  d->bad_iter = iter;
+  d->fail_iters = d->base + iter;
+}
+
+// Start a new LSQR solve in the state block after `base` iterations of the schedule; `first`
+// clears the sticky failure state.
+__global__ void k_lsqr_reset(LsqrDev* d, double damp, double gamma, int first, int base) {
   LsqrDev h = {};
   h.damp = damp;
   h.gamma = gamma;
   h.lambda = damp * damp;
   h.su = 1.0;
   h.sv = 1.0;
+  h.base = base;
   h.failed = first ? 0 : (d->failed || d->bad);
+  h.fail_iters = first ? 0 : d->fail_iters;
   *d = h;
 }
 
@@ -188,8 +200,7 @@ __global__ void k_lsqr_beta(LsqrDev* d) {
   if (stop(d)) return;
   const double b = sqrt(d->red);
   if (!isfinite(b)) {
-    d->bad = 1;
-    d->bad_iter = d->iter;
+    lsqr_fail(d, d->iter);
     return;
   }
   d->beta = b;
@@ -201,8 +212,7 @@ __global__ void k_lsqr_init_alpha(LsqrDev* d, int lambda_rule) {
   if (stop(d)) return;
   const double a = sqrt(d->red);
   if (!isfinite(a)) {
-    d->bad = 1;
-    d->bad_iter = 0;
+    lsqr_fail(d, 0);
     return;
   }
   d->alpha = a;
@@ -223,8 +233,7 @@ __global__ void k_lsqr_rotate(LsqrDev* d) {
   if (stop(d)) return;
   const double a = sqrt(d->red);
   if (!isfinite(a)) {
-    d->bad = 1;
-    d->bad_iter = d->iter;
+    lsqr_fail(d, d->iter);
     return;
   }
   d->alpha = a;
@@ -295,7 +304,7 @@ __global__ void k_scale_dev(T* __restrict__ y, const T* __restrict__ a, const do
 }
 
 struct FistaDev {
-  double L, lambda, rq, ww, vv, inv, amax;
+  double L, lambda, rq, ww, vv, inv, amax, ss;
   int bad;       // a non-finite value was met (sticky: later kernels do nothing)
   int bad_iter;  // FISTA iterations completed before it (0 in the power method / parameters)
 };
@@ -311,6 +320,12 @@ __global__ void k_power_scalars(FistaDev* f) {
   const double nw = sqrt(f->ww);
   f->inv = nw > 0 ? 1.0 / nw : 0.0;
   if (!isfinite(nw) || !isfinite(f->vv)) f->bad = 1;
+}
+
+// The signals enter FISTA only through A^T (A y - s), which reads the samples the model's
+// bands reach; ||s||^2 is tested once so that a non-finite sample anywhere stops the solve.
+__global__ void k_signal_check(FistaDev* f) {
+  if (!isfinite(f->ss)) f->bad = 1;
 }
 
 __global__ void k_power_start(FistaDev* f) {
@@ -470,7 +485,8 @@ class SolverT final : public Solver {
   // (b2 / gamma only for a correction solve of the refinement).
   int lsqr_init(const T* b1, const T* b2, T* xout, double damp, double gamma, int rule, int first) {
     const int gx = grid_for(nx_);
-    hipLaunchKernelGGL(k_lsqr_reset, dim3(1), dim3(1), 0, stream, d_, damp, b2 ? gamma : 0.0, first);
+    hipLaunchKernelGGL(k_lsqr_reset, dim3(1), dim3(1), 0, stream, d_, damp, b2 ? gamma : 0.0, first,
+                       phase_ * o_.iters);
     AROAM_HIP(hipMemcpyAsync(u_, b1, ns_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
     if (b2) AROAM_HIP(hipMemcpyAsync(u2_, b2, nx_ * sizeof(T), hipMemcpyDeviceToDevice, stream));
     hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
@@ -598,7 +614,7 @@ class SolverT final : public Solver {
     const bool bad = h.bad || h.failed;
     const int done = (int)std::min<long long>(enqueued_, (long long)phase_ * o_.iters + h.iter);
     if (info) {
-      info->iters_done = bad ? (int)((long long)phase_ * o_.iters + h.bad_iter) : done;
+      info->iters_done = bad ? h.fail_iters : done;
       info->status = bad ? AROAM_ENONFINITE : AROAM_OK;
       info->lambda = phase_ > 0 ? lam_ : h.lambda;
       info->lipschitz = 0.0;
@@ -631,6 +647,8 @@ class SolverT final : public Solver {
     }
     const int gx = grid_for(nx_);
     hipLaunchKernelGGL(k_fista_reset, dim3(1), dim3(1), 0, stream, f_);
+    AROAM_TRY(reduce_sq(s_, ns_, &f_->ss));
+    hipLaunchKernelGGL(k_signal_check, dim3(1), dim3(1), 0, stream, f_);
     if (npow_ > 0) {
       if (o_.power_start)
         AROAM_HIP(hipMemcpyAsync(v_, o_.power_start, nx_ * sizeof(T), hipMemcpyDeviceToDevice, stream));

@@ -1183,7 +1183,9 @@ int export_quantized(const Model& m, int dtype, bool adjoint, double* dense, flo
           const size_t pos = q * TM * G + (size_t)((r % kTile) * NH + h) * G + j;
           const float sc = gscale[q * NH + h];
           v = e4m3_value(raw[pos]) * (double)sc;
-          if (scales) scales[(size_t)gd.x * nblk + k / 16] = sc;
+          // a block with entries has a nonzero code (its largest lands in the top binade);
+          // the scale a pack carries for an empty block is not reported
+          if (scales && v != 0.0) scales[(size_t)gd.x * nblk + k / 16] = sc;
         }
         dense[((size_t)gd.x * nz + k) * nt + n] = v;
       }

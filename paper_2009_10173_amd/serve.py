@@ -107,7 +107,9 @@ def _progress(verbose, msg):
 
 
 def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbose=False):
-    """Replay the arrival times through the scheduler; returns per-request records."""
+    """Replay the arrival times through the scheduler; returns per-request records.  Also
+    counts the polls after which a request waited although a slot was free: the device-memory
+    budget held it back (admission by HBM footprint binding)."""
     import torch
     torch.cuda.synchronize()
     srv = B.aroam_server_create(budget_bytes, slots, tick)
@@ -115,7 +117,7 @@ def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbos
         order = sorted(range(len(reqs)), key=lambda i: reqs[i]["req"]["arrival_s"])
         by_id, rec = {}, {}
         t0 = time.perf_counter()
-        nxt, max_res = 0, 0
+        nxt, max_res, budget_waits = 0, 0, 0
         while len(rec) < len(reqs):
             now = time.perf_counter() - t0
             while nxt < len(order) and reqs[order[nxt]]["req"]["arrival_s"] * time_scale <= now:
@@ -126,6 +128,8 @@ def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbos
                 nxt += 1
             nres, nq = B.aroam_server_poll(srv)
             max_res = max(max_res, nres)
+            if nq > 0 and nres < slots:
+                budget_waits += 1
             done = B.aroam_server_collect(srv)
             tnow = time.perf_counter() - t0
             for rid, info in done:
@@ -143,7 +147,8 @@ def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbos
     finally:
         B.aroam_server_destroy(srv)
     return _summary(reqs, rec, mode, wall, extra=dict(max_resident=max_res, slots=slots,
-                                                      tick=tick, budget_bytes=budget_bytes))
+                                                      tick=tick, budget_bytes=budget_bytes,
+                                                      polls_held_by_budget=budget_waits))
 
 
 def run_fifo(reqs, mode, time_scale=1.0, verbose=False):
@@ -181,6 +186,32 @@ def _summary(reqs, rec, mode, wall, extra=None):
     return out
 
 
+def predicted_service(reqs, reps=3):
+    """FP32 one-at-a-time service time of each request, predicted from its pair count and the
+    measured time of one FP32 forward + adjoint pair of its model (HIP events, per distinct
+    model), instead of running the whole trace once to calibrate the arrival rate."""
+    import torch
+    pair_ms = {}
+    out = []
+    for r in reqs:
+        m = r["model"]
+        key = id(m)
+        if key not in pair_ms:
+            x = torch.zeros(m.image_shape, device=r["s"].device)
+            m.forward(x, "fp32")
+            m.adjoint(r["s"], "fp32", out=x)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                m.adjoint(m.forward(x, "fp32"), "fp32", out=x)
+            e1.record()
+            e1.synchronize()
+            pair_ms[key] = e0.elapsed_time(e1) / reps
+        out.append(pair_ms[key] * 1e-3 * pairs_of(r["req"], "fp32"))
+    return out
+
+
 def main(argv=None, quiet=False):
     import torch
     ap = argparse.ArgumentParser()
@@ -195,6 +226,11 @@ def main(argv=None, quiet=False):
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--rate", type=float, default=0.0,
                     help="arrival rate (requests/s); 0 calibrates it from the FIFO FP32 run")
+    ap.add_argument("--calibrate", default="run", choices=["run", "predict"],
+                    help="FP32 service time for the arrival rate: run the trace once one at a "
+                         "time, or predict it from each model's measured pair time")
+    ap.add_argument("--modes", default="fifo_fp32,served_fp32,served_bf16r",
+                    help="legs to run (comma-separated)")
     ap.add_argument("--verbose", action="store_true", help="print every completion")
     args = ap.parse_args(argv)
     W = _workloads()
@@ -211,6 +247,9 @@ def main(argv=None, quiet=False):
     if args.rate > 0:
         rate = args.rate
         service = args.load / rate
+    elif args.calibrate == "predict":
+        service = float(np.mean(predicted_service(reqs)))
+        rate = args.load / service
     else:
         for r in reqs:
             r["req"]["arrival_s"] = 0.0
@@ -222,14 +261,20 @@ def main(argv=None, quiet=False):
         r["req"]["arrival_s"] = tr["arrival_s"]
     print(f"[serve] FP32 service time {service:.3f} s/request -> Poisson rate {rate:.2f}/s",
           file=sys.stderr, flush=True)
-    res = dict(rate_per_s=rate, fp32_service_s=service)
-    res["fifo_fp32"] = run_fifo(reqs, "fp32", verbose=v)
-    print(f"[serve] fifo fp32 done", file=sys.stderr, flush=True)
+    res = dict(rate_per_s=rate, fp32_service_s=service, calibrate=args.calibrate,
+               sides=list(sides), nz=list(nzs), load=args.load)
+    modes = args.modes.split(",")
     budget = int(args.budget_gb * 2 ** 30)
-    res["served_fp32"] = run_served(reqs, "fp32", budget, args.slots, args.tick, verbose=v)
-    print(f"[serve] served fp32 done", file=sys.stderr, flush=True)
-    res["served_bf16r"] = run_served(reqs, "bf16r", budget, args.slots, args.tick, verbose=v)
-    print(f"[serve] served bf16r done", file=sys.stderr, flush=True)
+    for leg in modes:
+        if leg == "fifo_fp32":
+            res[leg] = run_fifo(reqs, "fp32", verbose=v)
+        elif leg in ("served_fp32", "served_bf16r"):
+            res[leg] = run_served(reqs, leg.split("_")[1], budget, args.slots, args.tick,
+                                  verbose=v)
+        else:
+            raise ValueError(f"unknown serving leg {leg}")
+        print(f"[serve] {leg} done: p50 {res[leg]['p50_s']:.2f} s, p99 {res[leg]['p99_s']:.2f} s",
+              file=sys.stderr, flush=True)
     cache.close()
     torch.cuda.synchronize()
     if not quiet:

@@ -320,20 +320,26 @@ def _raw_solve(fn_name, m, s, **opts):
     return rc, info
 
 
-def _nan_signal(cfg, seed=3):
+def _nan_signal(cfg, sample, seed=3):
     s = W.random_signal(cfg, seed)
-    s[3, 4, 10] = np.nan
+    s[3, 4, sample] = np.nan
     return s
 
 
+# a NaN at sample 10, which no band of the tiny model reaches (A^T never reads it), and at the
+# focal arrival nt / 2, inside the bands
+NAN_SAMPLES = [10, 64]
+
+
+@pytest.mark.parametrize("sample", NAN_SAMPLES)
 @pytest.mark.parametrize("how", ["explicit", "rule"])
-def test_nonfinite_signal_stops_fista(how):
-    """A NaN in s stops FISTA with AROAM_ENONFINITE: with explicit lambda and L at the first
-    gradient step (the soft threshold would map the NaN to 0, so the step is tested before it);
-    with the lambda rule in the parameters, since max|A^T s| carries the NaN through."""
+def test_nonfinite_signal_stops_fista(how, sample):
+    """A NaN in s stops FISTA with AROAM_ENONFINITE before any iteration, with explicit lambda
+    and L and with the lambda rule: s enters FISTA only through A^T (A y - s), which does not
+    read samples outside the bands, so ||s|| is tested at the set-up."""
     cfg = W.config("tiny")
     m = gpu_model("tiny")
-    s = t32(_nan_signal(cfg))
+    s = t32(_nan_signal(cfg, sample))
     if how == "explicit":
         rc, info = _raw_solve("aroam_solve_l1", m, s, lam=1e-3, lipschitz=1.0, iters=5)
     else:
@@ -355,14 +361,17 @@ def test_fista_divergence_reports_iterations_done():
     assert info.iters_done == 1
 
 
+@pytest.mark.parametrize("sample", NAN_SAMPLES)
 @pytest.mark.parametrize("inner", ["bf16", "fp32"])
-def test_nonfinite_signal_stops_refined_lsqr(inner):
-    """Refined LSQR with the lambda rule computes lambda from A^T s before the solve; a NaN in s
-    makes it non-finite, which is AROAM_ENONFINITE (not an argument error) with no iteration
-    done.  Plain LSQR stops at its first norm with iters_done = 0."""
+def test_nonfinite_signal_stops_refined_lsqr(inner, sample):
+    """Refined LSQR with the lambda rule computes lambda from A^T s before the solve: a NaN that
+    A^T reads makes lambda non-finite, which is AROAM_ENONFINITE (not an argument error); one
+    outside the bands leaves lambda finite and stops the first solve at its first norm.  Either
+    way no iteration is done, and iters_done says so although the schedule's later sweeps were
+    enqueued.  Plain LSQR stops at its first norm with iters_done = 0."""
     cfg = W.config("tiny")
     m = gpu_model("tiny")
-    s = t32(_nan_signal(cfg))
+    s = t32(_nan_signal(cfg, sample))
     rc, info = _raw_solve("aroam_solve_lsqr", m, s, lam=-1.0, iters=5, inner=inner,
                           outer="fp32", refine_sweeps=2)
     assert rc == -4 and info.status == -4 and info.iters_done == 0

@@ -56,14 +56,22 @@ def oracle_quantized(name, dtype):
     return Q.quantize_table(H, dtype, delta=1e-11 * np.max(np.abs(H)))
 
 
-def check_export(Hg, Hq, lo, hi, amb, label):
+# Largest share of the nonzero entries that may lie within delta of a rounding boundary.  An
+# entry far below the table's largest has an FP64 value known only to delta, which spans many
+# of its FP32 steps (about a third of the FP32 entries) or, below ~1e-6 of the largest, a BF16
+# step (about 1 %); e4m3 steps are relative to the block's scale, so almost none are.
+AMBIGUOUS_SHARE = {"fp32": 0.5, "bf16": 0.02, "fp8": 1e-3}
+
+
+def check_export(Hg, Hq, lo, hi, amb, label, dtype):
     n_amb = int(amb.sum())
-    print(f"[{label}] {n_amb} of {np.count_nonzero(Hq)} nonzero entries near a rounding "
-          f"boundary", flush=True)
-    assert n_amb <= 1e-3 * max(1, np.count_nonzero(Hq))
-    assert np.array_equal(Hg[~amb], Hq[~amb]), label
-    assert np.all((Hg[amb] == lo[amb]) | (Hg[amb] == hi[amb]) | ((Hg[amb] >= lo[amb]) &
-                                                                  (Hg[amb] <= hi[amb])))
+    n_nz = max(1, np.count_nonzero(Hq))
+    bad = int(np.count_nonzero(Hg[~amb] != Hq[~amb]))
+    print(f"[{label}] {n_amb} of {n_nz} nonzero entries near a rounding boundary; "
+          f"{bad} of the others differ", flush=True)
+    assert bad == 0, label
+    assert np.all((Hg[amb] >= lo[amb]) & (Hg[amb] <= hi[amb])), label
+    assert n_amb <= AMBIGUOUS_SHARE[dtype] * n_nz
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -76,7 +84,8 @@ def test_packed_table_matches_oracle_quantisation(name, dtype, adjoint):
     m = gpu_model(name)
     Hg, sc = m.export_quantized(dtype, adjoint)
     Hq, lo, hi, amb = oracle_quantized(name, dtype)
-    check_export(Hg, Hq, lo, hi, amb, f"{name} {dtype} {'adjoint' if adjoint else 'forward'}")
+    check_export(Hg, Hq, lo, hi, amb, f"{name} {dtype} {'adjoint' if adjoint else 'forward'}",
+                 dtype)
     if dtype == "fp8":
         H = oracle_table(name)
         sc_ref = Q.block_scales(H)
