@@ -16,7 +16,14 @@
  *     The voxel lateral grid coincides with the scan grid (Results, first paragraph).
  *     Element type: double for AROAM_FP64, float for every other dtype (AROAM_BF16 and
  *     AROAM_FP8E4M3 name the precision of the model table and operands inside the apply;
- *     accumulation is FP32 and the caller's vectors stay FP32).
+ *     the caller's vectors stay FP32).  AROAM_BF16: table and operand rounded to BF16
+ *     (nearest, ties to even), products accumulated in FP32.  AROAM_FP8E4M3: OCP e4m3 table
+ *     with a power-of-two scale per (offset, 16-depth block) and e4m3 operand with a
+ *     power-of-two scale per 64 entries of its fast axis (chosen from that block's largest
+ *     |value| over the call's whole input vector, the smallest power of two >= amax / 448),
+ *     multiplied on the block-scaled FP8 MFMA, which sums each 128-term product to about
+ *     14 bits (measured error below 1e-4 of the sum of absolute products), the sums
+ *     accumulated in FP32; NaN and infinities in the operand become e4m3 NaN codes.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Applies are asynchronous; the
  *     solvers enqueue all their work on `stream` and synchronise it once before returning.
  *   - Models are immutable after aroam_build_model and may be shared by concurrent calls on

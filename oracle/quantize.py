@@ -11,7 +11,7 @@ library primitive for rounding:
   scale per (lateral offset, block of 16 depths), the smallest power of two at or above
   amax / 448 with amax the largest |entry| of the FP64 table in the block; each entry is
   e4m3(fp32(v / scale)) * scale, rounded to nearest with ties to even.
-* FP8 operand: e4m3 codes of the FP32 vector divided by a power-of-two scale per block of 16
+* FP8 operand: e4m3 codes of the FP32 vector divided by a power-of-two scale per block of 64
   along its fast axis (depth of an image, time of a signal), chosen like the table's from the
   block's amax over all scan positions (see `operand_scales`); products are formed from the
   decoded values and accumulated in at least FP32.
@@ -30,7 +30,8 @@ import numpy as np
 import torch
 
 E4M3_MAX = 448.0
-BLOCK = 16  # depths per scale block of the FP8 table
+BLOCK = 16          # depths per scale block of the FP8 table
+OPERAND_BLOCK = 64  # entries of the fast axis per scale block of the FP8 operand
 
 
 def fp32(a):
@@ -138,12 +139,13 @@ def quantize_table(H, dtype, delta):
     return Hq, lo, hi, lo != hi
 
 
-def operand_scales(v, axis_len):
-    """Power-of-two scale per block of 16 along the fast axis of a vector [ny][nx][L]: the
-    smallest power of two >= amax / 448 of the block over all scan positions."""
+def operand_scales(v, axis_len, block=OPERAND_BLOCK):
+    """Power-of-two scale per block of `block` entries along the fast axis of a vector
+    [ny][nx][L]: the smallest power of two >= amax / 448 of the block over all scan positions
+    (0 for a block of zeros)."""
     v = np.asarray(v, dtype=np.float64).reshape(-1, axis_len)
-    nblk = -(-axis_len // BLOCK)
-    amax = np.array([np.max(np.abs(v[:, BLOCK * b:BLOCK * (b + 1)])) for b in range(nblk)])
+    nblk = -(-axis_len // block)
+    amax = np.array([np.max(np.abs(v[:, block * b:block * (b + 1)])) for b in range(nblk)])
     return pow2_scale(amax)
 
 
@@ -157,7 +159,7 @@ def quantize_operand(v, dtype):
         return bf16(v)
     if dtype == "fp8-operand":
         L = v.shape[-1]
-        sc = np.repeat(operand_scales(v, L), BLOCK)[:L]
+        sc = np.repeat(operand_scales(v, L), OPERAND_BLOCK)[:L]
         with np.errstate(invalid="ignore", divide="ignore"):
             q = np.where(sc > 0, v / np.where(sc > 0, sc, 1.0), 0.0)
         return e4m3(fp32(q)) * sc

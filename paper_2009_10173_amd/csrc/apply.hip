@@ -10,8 +10,9 @@
 // of the padded input supplies the zeros outside the region of interest.
 //
 // GEMM view per tile: M = 16 output rows, N = scan positions (16 per MFMA), K = the tile's
-// K-groups.  Kernels: a plain FP64/FP32 FMA kernel, FP32 MFMA (v_mfma_f32_16x16x4f32) and
-// BF16 MFMA (v_mfma_f32_16x16x32_bf16) on gfx950.
+// K-groups.  Kernels: a plain FP64/FP32 FMA kernel, FP32 MFMA (v_mfma_f32_16x16x4f32), BF16
+// MFMA (v_mfma_f32_16x16x32_bf16) and the block-scaled FP8 MFMA
+// (v_mfma_scale_f32_16x16x128_f8f6f4, e4m3 table and operand) on gfx950.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +33,8 @@ typedef float floatx2 __attribute__((ext_vector_type(2)));
 // no local variable has its address taken (which would place it in scratch memory).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 
 
 template <typename Tin, typename Tout>
@@ -110,57 +113,28 @@ struct StagedArgs {
   int NCOL, CS;
 };
 
-// Table operand of one bundle for one lane: 16 bytes per half (FP32 / BF16), or 8 bytes of
-// e4m3 per half (both halves in one 16-byte load) plus the K-group's scale per half.
-// MH 16-row halves of the tile (MH = TM / 16).
-template <typename T, bool FP8A, int MH>
+// Table operand of one bundle for one lane: 16 bytes per 16-row half (MH = TM / 16 halves).
+template <typename T, int MH>
 struct AFrag {
   u32x4 v[MH];
-  float sc[MH];
   int mo;
   int hm;  // halves to issue (bit h: half h); uniform over the wave
 };
 
-template <typename T, bool FP8A, int MH>
+template <typename T, int MH>
 __device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
-                                       const float* __restrict__ gscale,
                                        const int* __restrict__ meta,
                                        const int* __restrict__ bmask, int b, int g, int n,
-                                       AFrag<T, FP8A, MH>& f) {
+                                       AFrag<T, MH>& f) {
   const int q = b * kLaneGroups + g;
-  if constexpr (FP8A) {
-    // e4m3: the lane's 8 entries of both halves in one 16-byte load, both scales in one
-    static_assert(MH == 2, "FP8 tiles have two 16-row halves");
-    const u32x4 r = *reinterpret_cast<const u32x4*>(reinterpret_cast<const uint8_t*>(pack_raw) +
-                                                    ((long long)q * 16 + n) * 16);
-    const floatx2 sc = *reinterpret_cast<const floatx2*>(gscale + (long long)q * 2);
-    f.v[0] = u32x4{r.x, r.y, 0u, 0u};
-    f.v[1] = u32x4{r.z, r.w, 0u, 0u};
-    f.sc[0] = sc.x;
-    f.sc[1] = sc.y;
-  } else {
 #pragma unroll
-    for (int h = 0; h < MH; ++h) {
-      const long long row = (long long)q * (16 * MH) + 16 * h + n;
-      constexpr int VEC = 16 / sizeof(T);
-      f.v[h] = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(pack_raw) + row * VEC);
-      f.sc[h] = 1.0f;
-    }
+  for (int h = 0; h < MH; ++h) {
+    const long long row = (long long)q * (16 * MH) + 16 * h + n;
+    constexpr int VEC = 16 / sizeof(T);
+    f.v[h] = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(pack_raw) + row * VEC);
   }
   f.mo = meta[q];
   f.hm = MH > 1 ? bmask[b] : 1;
-}
-
-// e4m3 entries of a fragment -> BF16 operand with the K-group's scale applied.  The scales
-// are powers of two, so the scaled conversion (which applies the exponent of its scale
-// operand) is exact up to the BF16 rounding.
-__device__ __forceinline__ u32x4 decode_fp8(u32x4 v, float sc) {
-  const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, sc, false);
-  const bf16x2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, sc, true);
-  const bf16x2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, sc, false);
-  const bf16x2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, sc, true);
-  return u32x4{__builtin_bit_cast(unsigned, p0), __builtin_bit_cast(unsigned, p1),
-               __builtin_bit_cast(unsigned, p2), __builtin_bit_cast(unsigned, p3)};
 }
 
 // Global source and LDS destination of flat stage vector idx of a unit that loads padded
@@ -246,15 +220,13 @@ __device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int
 }
 
 // MFMAs of one bundle whose position fragments are already in registers.
-template <typename T, bool FP8A, int MH, int NT>
-__device__ __forceinline__ void bundle_mma(const AFrag<T, FP8A, MH>& f, const u32x4 (&xraw)[NT],
+template <typename T, int MH, int NT>
+__device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&xraw)[NT],
                                            floatx4 (&acc)[MH][NT]) {
 #pragma unroll
   for (int h = 0; h < MH; ++h) {
     if (MH > 1 && !((f.hm >> h) & 1)) continue;  // the bundle's bands miss this half
-    u32x4 araw;
-    if constexpr (FP8A) araw = decode_fp8(f.v[h], f.sc[h]);
-    else araw = f.v[h];
+    const u32x4 araw = f.v[h];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if constexpr (sizeof(T) == 4) {
@@ -283,9 +255,8 @@ __device__ __forceinline__ void bundle_mma(const AFrag<T, FP8A, MH>& f, const u3
 // PD-deep register ring that runs across unit boundaries.  Lane (n = lane % 16,
 // g = lane / 16) holds row n of K-group g of the table and the entries of K-group g for
 // position n.
-template <typename T, int BR, int BC, bool FP8A, int MH>
+template <typename T, int BR, int BC, int MH>
 __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ pack_raw,
-                                                      const float* __restrict__ gscale,
                                                       const T* __restrict__ in,
                                                       float* __restrict__ out, StagedArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -321,12 +292,12 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
     // table fragments stream through a ring of PD slots per stage unit, unrolled so that
     // every slot stays in fixed registers (shifting a ring would move registers that loads
     // in flight still target, which forces full waits)
-    AFrag<T, FP8A, MH> ring[PD];
+    AFrag<T, MH> ring[PD];
     {
       const int4 U = a.units[u0];
 #pragma unroll
       for (int j = 0; j < PD; ++j)
-        load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(U.z + j, U.w - 1), g, n, ring[j]);
+        load_a<T, MH>(pack_raw, a.meta, a.bmask, min(U.z + j, U.w - 1), g, n, ring[j]);
       stage_prefetch<T, RS, PF>(a, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
       stage_rows<T, RS, PF>(a, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
       __syncthreads();
@@ -352,15 +323,14 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
           for (int j = 0; j < PD; ++j) {
             // slot (j + 1) mod PD holds the next bundle (or a clamped copy of the last one)
             read_x<T, NT>(lds, lbase, ring[(j + 1) % PD].mo, (j % 2) ? xa : xb);
-            if (b0 + j < U.w) bundle_mma<T, FP8A, MH, NT>(ring[j], (j % 2) ? xb : xa, acc);
+            if (b0 + j < U.w) bundle_mma<T, MH, NT>(ring[j], (j % 2) ? xb : xa, acc);
             // refill unconditionally (clamped to the unit's last bundle) so that the number
             // of loads in flight is fixed and the waits can count them
-            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n,
-                                ring[j]);
+            load_a<T, MH>(pack_raw, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
           }
         }
       } else {
-        // BF16 / FP8: one register set for the position fragments (a second one would cost
+        // BF16: one register set for the position fragments (a second one would cost
         // the third wave per SIMD, or a shorter table ring, both measured slower)
         for (int b0 = U.z; b0 < U.w; b0 += PD) {
 #pragma unroll
@@ -368,10 +338,9 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
             if (b0 + j < U.w) {
               u32x4 x[NT];
               read_x<T, NT>(lds, lbase, ring[j].mo, x);
-              bundle_mma<T, FP8A, MH, NT>(ring[j], x, acc);
+              bundle_mma<T, MH, NT>(ring[j], x, acc);
             }
-            load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n,
-                                ring[j]);
+            load_a<T, MH>(pack_raw, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
           }
         }
       }
@@ -381,8 +350,7 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
         // the next unit's first table fragments; their loads overlap the staging below
 #pragma unroll
         for (int j = 0; j < PD; ++j)
-          load_a<T, FP8A, MH>(pack_raw, gscale, a.meta, a.bmask, min(Un.z + j, Un.w - 1), g, n,
-                              ring[j]);
+          load_a<T, MH>(pack_raw, a.meta, a.bmask, min(Un.z + j, Un.w - 1), g, n, ring[j]);
         // one new row right after this unit's rows: its slot is the free one
         const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
         if (!free_slot) __syncthreads();  // every wave is done reading the rows replaced
@@ -456,6 +424,298 @@ __global__ __launch_bounds__(256) void k_add_slots(const int2* __restrict__ tile
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// FP8 applies: e4m3 table and e4m3 operand on the block-scaled FP8 MFMA
+// (v_mfma_scale_f32_16x16x128_f8f6f4).  The operand (image or signals) gets one power-of-two
+// scale per chunk of 64 entries of its fast axis over all scan positions, so every K-group of a
+// stage unit (one chunk) shares it; the table's scale per (offset, 16-depth block) is carried
+// per scale block of a bundle (see the layout).
+
+// NaN-carrying maximum (fmaxf drops a NaN).
+__device__ inline float nan_maxf(float a, float b) { return (a > b || a != a) ? a : b; }
+
+// part[c * nparts + p] = max |in| over the entries of chunk c (64 entries of the fast axis) of
+// the scan positions p, p + nparts, ...  Grid (nparts, chunks); 256 threads = 4 positions x 64.
+__global__ __launch_bounds__(256) void k_chunk_amax(const float* __restrict__ in, long long npos,
+                                                    int L, float* __restrict__ part) {
+  __shared__ float sh[256];
+  const int c = blockIdx.y, nparts = gridDim.x;
+  const int e = threadIdx.x % 64, r = threadIdx.x / 64;
+  const int l = c * 64 + e;
+  float m = 0.0f;
+  if (l < L)
+    for (long long i = blockIdx.x + (long long)nparts * r; i < npos; i += 4LL * nparts)
+      m = nan_maxf(m, fabsf(in[i * L + l]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = nan_maxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)c * nparts + blockIdx.x] = sh[0];
+}
+
+// Per chunk: the smallest power of two 2^e >= amax / 448 (e = 0 for a chunk of zeros or a
+// non-finite amax, whose NaN codes then reach the output), as the E8M0 byte e + 127 and 2^-e.
+// 448 = 0.875 2^9, so with amax = m 2^ea (0.5 <= m < 1): e = ea - 9 if m <= 0.875, else ea - 8.
+__global__ void k_chunk_scales(const float* __restrict__ part, int nparts, int nch,
+                               int* __restrict__ xexp, float* __restrict__ xinv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  float a = 0.0f;
+  for (int p = 0; p < nparts; ++p) a = nan_maxf(a, part[(long long)c * nparts + p]);
+  int e = 0;
+  if (a > 0.0f && a <= 3.402823466e38f) {
+    int ea;
+    const float mnt = frexpf(a, &ea);
+    e = mnt <= 0.875f ? ea - 9 : ea - 8;
+  }
+  e = max(-126, min(127, e));
+  xexp[c] = e + 127;
+  xinv[c] = ldexpf(1.0f, -e);
+}
+
+// Stage an FP32 input into the zero-padded e4m3 layout [nyp][nxp][Lp] (codes of x 2^-e of its
+// chunk); one workgroup per padded column, as k_stage.
+__global__ __launch_bounds__(256) void k_stage_fp8(const float* __restrict__ in,
+                                                   uint8_t* __restrict__ out,
+                                                   const float* __restrict__ xinv, int K, int nx,
+                                                   int ny, int nxp, int L, int Lp) {
+  const int col = blockIdx.x;
+  const int px = col % nxp - K, py = col / nxp - K;
+  uint8_t* o = out + (long long)col * Lp;
+  const bool inside = px >= 0 && px < nx && py >= 0 && py < ny;
+  const float* src = in + ((long long)py * nx + px) * L;
+  for (int l = threadIdx.x; l < Lp; l += blockDim.x) {
+    uint8_t v = 0;
+    if (inside && l < L) v = f32_to_e4m3(src[l] * xinv[l / 64]);
+    o[l] = v;
+  }
+}
+
+struct Fp8Args {
+  const int4* pieces;
+  const int2* tile_split;
+  float* partial;
+  int n_patches;
+  const int4* units;
+  const int2* urows;
+  const u32x4* rec;   // per bundle and lane group: LDS offsets of its 4 K-groups (16 bits
+                      // each), the E8M0 scale bytes of its block for the two halves; word 3
+                      // of lane group 0: the 16-row halves the bundle's K-groups reach
+  const int* xexp;    // per chunk of the operand: E8M0 scale byte
+  int out_len, nx, ny, K, nxp, Lp;
+  int ncc;
+  int NCOL, CS;
+};
+
+// Table operand of one FP8 bundle for one lane: 32 bytes per half, and the bundle's record
+// (16 words, the same for the whole wave, so it comes through the scalar path: word 4 g + i
+// of lane group g; word 3 holds the half mask).
+struct F8Frag {
+  u32x4 v[2][2];
+  uint32_t w[16];
+};
+
+__device__ __forceinline__ void load_f8(const uint8_t* __restrict__ pack, const Fp8Args& a,
+                                        int b, int lane, F8Frag& f) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(pack + (((long long)b * 2 + h) * 64 + lane) * 32);
+    f.v[h][0] = p[0];
+    f.v[h][1] = p[1];
+  }
+  const uint32_t* r = reinterpret_cast<const uint32_t*>(a.rec) + (long long)b * 16;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) f.w[i] = r[i];
+}
+
+// Word i of lane group g's part of a bundle record, selected with masks (no branches):
+// m1 / m2 are all ones where bit 0 / bit 1 of g is set.
+__device__ __forceinline__ uint32_t rec_word(const F8Frag& f, uint32_t m1, uint32_t m2, int i) {
+  const uint32_t lo = (f.w[i] & ~m1) | (f.w[4 + i] & m1);
+  const uint32_t hi = (f.w[8 + i] & ~m1) | (f.w[12 + i] & m1);
+  return (lo & ~m2) | (hi & m2);
+}
+
+// LDS offsets of the lane group's four K-groups in an FP8 bundle.
+struct X8Offs {
+  int o[4];
+};
+
+__device__ __forceinline__ X8Offs x8_offsets(const F8Frag& f, uint32_t m1, uint32_t m2) {
+  const uint32_t r0 = rec_word(f, m1, m2, 0), r1 = rec_word(f, m1, m2, 1);
+  return X8Offs{{(int)(r0 & 0xffff), (int)(r0 >> 16), (int)(r1 & 0xffff), (int)(r1 >> 16)}};
+}
+
+// Position fragments of one FP8 bundle for the NT tiles of this lane: for each of the lane
+// group's four K-groups, 8 bytes of the lane's position from the LDS.
+template <int NT>
+__device__ __forceinline__ void read_x8(const uint8_t* lds, const int (&lbase)[NT], const X8Offs& o,
+                                        u32x4 (&x)[NT][2]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const u32x2 q0 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[0]);
+    const u32x2 q1 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[1]);
+    const u32x2 q2 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[2]);
+    const u32x2 q3 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[3]);
+    x[t][0] = u32x4{q0.x, q0.y, q1.x, q1.y};
+    x[t][1] = u32x4{q2.x, q2.y, q3.x, q3.y};
+  }
+}
+
+// The block-scaled MFMAs of one FP8 bundle: per reached half h (bit h of hm) and position tile,
+// 16 rows x 128 K x 16 positions, with the lane's block scale byte h of sc and the unit's
+// operand scale xs.
+template <int NT>
+__device__ __forceinline__ void fp8_mma(const F8Frag& f, int sc, int hm, int xs,
+                                        const u32x4 (&x)[NT][2], floatx4 (&acc)[2][NT]) {
+  if (hm & 1) {
+    const intx8 av = __builtin_bit_cast(
+        intx8, u32x8{f.v[0][0].x, f.v[0][0].y, f.v[0][0].z, f.v[0][0].w, f.v[0][1].x, f.v[0][1].y,
+                     f.v[0][1].z, f.v[0][1].w});
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const intx8 bv = __builtin_bit_cast(intx8, u32x8{x[t][0].x, x[t][0].y, x[t][0].z, x[t][0].w,
+                                                       x[t][1].x, x[t][1].y, x[t][1].z, x[t][1].w});
+      acc[0][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[0][t], 0, 0, 0, sc,
+                                                                   0, xs);
+    }
+  }
+  if (hm & 2) {
+    const intx8 av = __builtin_bit_cast(
+        intx8, u32x8{f.v[1][0].x, f.v[1][0].y, f.v[1][0].z, f.v[1][0].w, f.v[1][1].x, f.v[1][1].y,
+                     f.v[1][1].z, f.v[1][1].w});
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const intx8 bv = __builtin_bit_cast(intx8, u32x8{x[t][0].x, x[t][0].y, x[t][0].z, x[t][0].w,
+                                                       x[t][1].x, x[t][1].y, x[t][1].z, x[t][1].w});
+      acc[1][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[1][t], 0, 0, 1, sc,
+                                                                   0, xs);
+    }
+  }
+}
+
+// LDS-staged FP8 kernel: the staged kernel's workgroup shape, LDS row ring and unit order
+// (BR x BC position patch, 32-row tile of two 16-row halves, NT 16-position tiles per wave),
+// with bundles of 16 K-groups: per half and position tile one block-scaled MFMA of K = 128.
+// Lane (n, g) reads, for each of its lane group's four K-groups, 8 bytes of position n from
+// the LDS (the K-group's column and run) and 32 bytes of table row n per half.
+// Two waves per SIMD: the 160 KiB LDS holds at most two workgroups of the 81 x 81 footprint
+// (K = 40) anyway, and the larger register budget keeps the table stage's next-row fetch and
+// the ring's loads counted (no full vmcnt wait per bundle).
+template <int BR, int BC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply_fp8(const uint8_t* __restrict__ pack,
+                                                   const uint8_t* __restrict__ in,
+                                                   float* __restrict__ out, Fp8Args a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  uint8_t* lds = lds_raw;
+  constexpr int TPR = BC / 16;
+  constexpr int RW = BR / 4;
+  constexpr int NT = RW * TPR;
+  constexpr int PF = 4;
+  constexpr int PD = 2;                // table-fragment ring depth (bundles)
+  constexpr int MH = 2;
+  const int4 piece = a.pieces[blockIdx.y];
+  const int tile = piece.x;
+  const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int n = lane % 16, g = lane / 16;
+  const uint32_t m1 = 0u - (uint32_t)(g & 1), m2 = 0u - (uint32_t)((g >> 1) & 1);
+  constexpr int nvec = 4;              // 16-byte vectors per staged column (64-byte chunk)
+  const int rowvec = a.NCOL * nvec;
+  StagedArgs sa;                       // the staging helpers' view of the arguments
+  sa.units = a.units;
+  sa.urows = a.urows;
+  sa.NCOL = a.NCOL;
+  sa.CS = a.CS;
+  sa.nxp = a.nxp;
+  sa.Lp = a.Lp;
+  floatx4 acc[MH][NT];
+#pragma unroll
+  for (int h = 0; h < MH; ++h)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[h][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int u0 = piece.y, u1 = piece.z;
+  if (u0 < u1) {
+    constexpr int RS = BR + 1;
+    u32x4 pf[PF];
+    int pf_off[PF];
+    F8Frag ring[PD];
+    {
+      const int4 U = a.units[u0];
+#pragma unroll
+      for (int j = 0; j < PD; ++j) load_f8(pack, a, min(U.z + j, U.w - 1), lane, ring[j]);
+      stage_prefetch<uint8_t, RS, PF>(sa, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
+      stage_rows<uint8_t, RS, PF>(sa, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
+      __syncthreads();
+      if (u0 + 1 < u1) stage_prefetch<uint8_t, RS, PF>(sa, in, u0 + 1, py0, px0, rowvec, nvec, pf, pf_off);
+    }
+    for (int u = u0; u < u1; ++u) {
+      const int4 U = a.units[u];
+      const int xs = a.xexp[U.y / 64];  // the unit's chunk: one operand scale
+      const int R = U.x + a.K;
+      int lbase[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
+        lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
+      }
+      // the next bundle's position fragments are read while this bundle's MFMAs run (two
+      // register sets; ring slot (j + 1) mod PD holds the next bundle or a clamped copy)
+      // The bundle's record words come through the scalar path, whose loads complete out of
+      // order, so their first use waits for every LDS read in flight too: the current bundle's
+      // scale and mask and the next bundle's offsets are taken before the next bundle's reads
+      // are issued (the scheduling barriers keep that order).
+      u32x4 xa[NT][2], xb[NT][2];
+      read_x8<NT>(lds, lbase, x8_offsets(ring[0], m1, m2), xa);
+      for (int b0 = U.z; b0 < U.w; b0 += PD) {
+#pragma unroll
+        for (int j = 0; j < PD; ++j) {
+          const int sc = (int)rec_word(ring[j], m1, m2, 2);
+          const int hm = b0 + j < U.w ? (int)ring[j].w[3] : 0;
+          const X8Offs on = x8_offsets(ring[(j + 1) % PD], m1, m2);
+          __builtin_amdgcn_sched_barrier(0);
+          read_x8<NT>(lds, lbase, on, (j % 2) ? xa : xb);
+          __builtin_amdgcn_sched_barrier(0);
+          fp8_mma<NT>(ring[j], sc, hm, xs, (j % 2) ? xb : xa, acc);
+          load_f8(pack, a, min(b0 + j + PD, U.w - 1), lane, ring[j]);
+        }
+      }
+      if (u + 1 < u1) {
+        const int4 Un = a.units[u + 1];
+        const int2 Rn = a.urows[u + 1];
+#pragma unroll
+        for (int j = 0; j < PD; ++j) load_f8(pack, a, min(Un.z + j, Un.w - 1), lane, ring[j]);
+        const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
+        if (!free_slot) __syncthreads();
+        stage_rows<uint8_t, RS, PF>(sa, in, lds, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
+        __syncthreads();
+        if (u + 2 < u1) stage_prefetch<uint8_t, RS, PF>(sa, in, u + 2, py0, px0, rowvec, nvec, pf, pf_off);
+      }
+    }
+  }
+  constexpr int PS = BR * BC * 16 * MH;
+  float* slot =
+      piece.w >= 0 ? a.partial + ((long long)piece.w * a.n_patches + blockIdx.x) * PS : nullptr;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int py = py0 + wave * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
+    if (py >= a.ny || px >= a.nx) continue;
+    const int local = (wave * RW + t / TPR) * BC + (t % TPR) * 16 + n;
+    float* dst = slot ? slot : out;
+    const long long off = slot ? (long long)local * (16 * MH) - 16 * MH * tile
+                               : ((long long)py * a.nx + px) * a.out_len;
+#pragma unroll
+    for (int h = 0; h < MH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * MH * tile + 16 * h + 4 * g + i;
+        if (row < a.out_len) dst[off + row] = acc[h][t][i];
+      }
+  }
+}
+
 ApplyArgs make_args(const Layout& lay) {
   ApplyArgs a;
   a.tile_start = lay.d_tile_start;
@@ -474,24 +734,31 @@ size_t elem_bytes(int dtype) {
   switch (dtype) {
     case AROAM_FP64: return 8;
     case AROAM_FP32: return 4;
-    default: return 2;  // BF16 and FP8 stage their vector operand as BF16
+    case AROAM_BF16: return 2;
+    default: return 1;  // e4m3
   }
 }
+
+constexpr int kAmaxParts = 64;  // position slices of the FP8 operand's chunk maxima
 
 }  // namespace
 
 const Layout& layout_for(const Model& m, bool adjoint, int dtype) {
   if (dtype == AROAM_FP64) return adjoint ? m.g4a : m.g4f;
   if (dtype == AROAM_FP32) return adjoint ? m.s4a : m.s4f;
-  return adjoint ? m.s8a : m.s8f;
+  if (dtype == AROAM_BF16) return adjoint ? m.s8a : m.s8f;
+  return adjoint ? m.f8a : m.f8f;
 }
 
 namespace {
 
 // The stage buffer of an apply: the padded input, then, for a staged layout with cut tiles,
-// the partial slots [slot][patch][position of the patch][TM rows] (FP32).
+// the partial slots [slot][patch][position of the patch][TM rows] (FP32), then for FP8 the
+// operand's chunk scales: partial maxima [chunk][kAmaxParts] (FP32), E8M0 bytes [chunk] (int)
+// and inverse scales [chunk] (FP32).
 struct StageParts {
-  size_t input = 0, partial = 0;
+  size_t input = 0, partial = 0, scales = 0;
+  int chunks = 0;
 };
 
 StageParts stage_parts(const Model& m, bool adjoint, int dtype) {
@@ -502,6 +769,10 @@ StageParts stage_parts(const Model& m, bool adjoint, int dtype) {
     p.partial = (size_t)lay.n_slots * lay.n_patches * lay.TM * kPatchRows * kPatchCols *
                 sizeof(float);
   }
+  if (dtype == AROAM_FP8E4M3) {
+    p.chunks = (int)ceil_div(lay.in.L, 64);
+    p.scales = (size_t)round_up((size_t)p.chunks * (kAmaxParts + 2) * 4, 256);
+  }
   return p;
 }
 
@@ -509,17 +780,17 @@ StageParts stage_parts(const Model& m, bool adjoint, int dtype) {
 
 size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
   const StageParts p = stage_parts(m, adjoint, dtype);
-  return p.input + p.partial;
+  return p.input + p.partial + p.scales;
 }
 
 namespace {
 
-template <typename T, bool FP8A, int MH>
+template <typename T, int MH>
 int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* partial, void* out,
                   hipStream_t st) {
   static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
   AROAM_CHECK(lay.TM == 16 * MH, AROAM_EINVAL, "tile height mismatch");
-  auto kern = k_apply_staged<T, kPatchRows, kPatchCols, FP8A, MH>;
+  auto kern = k_apply_staged<T, kPatchRows, kPatchCols, MH>;
   // allow the full LDS of a CU for wide footprints, once per device
   static std::atomic<unsigned long long> attr_set{0};
   int dev = 0;
@@ -555,8 +826,8 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
               "patch count mismatch");
   AROAM_CHECK(lay.n_slots == 0 || partial, AROAM_EINVAL, "no partial slots for a cut layout");
   const dim3 grid((unsigned)lay.n_patches, (unsigned)lay.n_pieces);
-  hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const void*)pk.d,
-                     (const float*)pk.d_scale, (const T*)buf, (float*)out, a);
+  hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const void*)pk.d, (const T*)buf,
+                     (float*)out, a);
   if (lay.n_slots > 0)
     hipLaunchKernelGGL((k_add_slots<kPatchRows, kPatchCols, MH>),
                        dim3((unsigned)lay.n_patches, (unsigned)lay.n_tiles), dim3(256), 0, st,
@@ -570,12 +841,87 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
 namespace {
 
 // The launches of one apply into the stage buffer `buf` (stage_bytes() bytes).
+// Allow the full LDS of a CU for a kernel, once per device.
+template <typename F>
+int allow_full_lds(F kern, std::atomic<unsigned long long>& done) {
+  int dev = 0;
+  AROAM_HIP(hipGetDevice(&dev));
+  const unsigned long long bit = 1ull << (dev & 63);
+  if (!(done.load() & bit)) {
+    AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kLdsBytes));
+    done.fetch_or(bit);
+  }
+  return AROAM_OK;
+}
+
+// FP8 apply: chunk maxima and scales of the operand, the e4m3 staging, the staged FP8 kernel,
+// and the slot sums of cut tiles.
+int launch_fp8(const Model& m, const Layout& lay, const Pack& pk, const float* in, void* buf,
+               const StageParts& sp, void* out, hipStream_t st) {
+  auto kern = k_apply_fp8<kPatchRows, kPatchCols>;
+  static std::atomic<unsigned long long> attr_set{0};
+  AROAM_TRY(allow_full_lds(kern, attr_set));
+  AROAM_CHECK(lay.TM == kTileRows8 && lay.CH == 64 && lay.CS == kColumnBytes, AROAM_EINVAL,
+              "FP8 layout shape mismatch");
+  const PadGeom& pg = lay.in;
+  char* base = static_cast<char*>(buf);
+  uint8_t* staged = reinterpret_cast<uint8_t*>(base);
+  float* partial = sp.partial > 0 ? reinterpret_cast<float*>(base + sp.input) : nullptr;
+  float* amax = reinterpret_cast<float*>(base + sp.input + sp.partial);
+  int* xexp = reinterpret_cast<int*>(amax + (size_t)sp.chunks * kAmaxParts);
+  float* xinv = reinterpret_cast<float*>(xexp + sp.chunks);
+  const long long npos = (long long)pg.nx * pg.ny;
+  hipLaunchKernelGGL(k_chunk_amax, dim3(kAmaxParts, (unsigned)sp.chunks), dim3(256), 0, st, in,
+                     npos, pg.L, amax);
+  hipLaunchKernelGGL(k_chunk_scales, dim3((unsigned)ceil_div(sp.chunks, 64)), dim3(64), 0, st,
+                     (const float*)amax, kAmaxParts, sp.chunks, xexp, xinv);
+  hipLaunchKernelGGL(k_stage_fp8, dim3((unsigned)(pg.nyp * pg.nxp)), dim3(256), 0, st, in, staged,
+                     (const float*)xinv, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp);
+  Fp8Args a;
+  a.pieces = lay.d_pieces;
+  a.tile_split = lay.d_tile_split;
+  a.partial = partial;
+  a.n_patches = lay.n_patches;
+  a.units = lay.d_units;
+  a.urows = lay.d_ucols;
+  a.rec = reinterpret_cast<const u32x4*>(lay.d_meta);
+  a.xexp = xexp;
+  a.out_len = lay.out_len;
+  a.nx = pg.nx;
+  a.ny = pg.ny;
+  a.K = pg.K;
+  a.nxp = pg.nxp;
+  a.Lp = pg.Lp;
+  a.ncc = (int)ceil_div(pg.nx, kPatchCols);
+  a.NCOL = lay.NCOL;
+  a.CS = lay.CS;
+  AROAM_CHECK(lay.n_patches == ceil_div(pg.ny, kPatchRows) * a.ncc, AROAM_EINVAL,
+              "patch count mismatch");
+  AROAM_CHECK(lay.n_slots == 0 || partial, AROAM_EINVAL, "no partial slots for a cut layout");
+  const dim3 grid((unsigned)lay.n_patches, (unsigned)lay.n_pieces);
+  hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const uint8_t*)pk.d,
+                     (const uint8_t*)staged, (float*)out, a);
+  if (lay.n_slots > 0)
+    hipLaunchKernelGGL((k_add_slots<kPatchRows, kPatchCols, 2>),
+                       dim3((unsigned)lay.n_patches, (unsigned)lay.n_tiles), dim3(256), 0, st,
+                       lay.d_tile_split, (const float*)partial, (float*)out, lay.n_patches, a.ncc,
+                       a.nx, a.ny, a.out_len);
+  return AROAM_OK;
+}
+
 int launch_apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* buf,
                  hipStream_t st) {
   const Layout& lay = layout_for(m, adjoint, dtype);
   const Pack& pk = adjoint ? m.adj_pack[dtype] : m.fwd_pack[dtype];
   const PadGeom& pg = lay.in;
   const dim3 sgrid((unsigned)(pg.nyp * pg.nxp));
+  if (dtype == AROAM_FP8E4M3) {
+    AROAM_TRY(launch_fp8(m, lay, pk, (const float*)in, buf, stage_parts(m, adjoint, dtype), out,
+                         st));
+    AROAM_HIP(hipGetLastError());
+    return AROAM_OK;
+  }
   if (dtype == AROAM_FP64)
     hipLaunchKernelGGL((k_stage<double, double>), sgrid, dim3(256), 0, st, (const double*)in,
                        (double*)buf, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp);
@@ -595,11 +941,9 @@ int launch_apply(const Model& m, bool adjoint, int dtype, const void* in, void* 
     float* partial =
         sp.partial > 0 ? reinterpret_cast<float*>(static_cast<char*>(buf) + sp.input) : nullptr;
     if (dtype == AROAM_FP32)
-      AROAM_TRY((launch_staged<float, false, 1>(lay, pk, buf, partial, out, st)));
-    else if (dtype == AROAM_BF16)
-      AROAM_TRY((launch_staged<uint16_t, false, kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
+      AROAM_TRY((launch_staged<float, 1>(lay, pk, buf, partial, out, st)));
     else
-      AROAM_TRY((launch_staged<uint16_t, true, kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
+      AROAM_TRY((launch_staged<uint16_t, kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
   }
   AROAM_HIP(hipGetLastError());
   return AROAM_OK;

@@ -112,10 +112,18 @@ struct Layout {
 };
 
 struct Pack {
-  void* d = nullptr;   // [n_bundles * 4 * TM * G] elements of the dtype
-  float* d_scale = nullptr;  // FP8 only: FP32 scale per (K-group, 16-row half)
+  void* d = nullptr;   // FP32 / BF16: [n_bundles * 4 * TM * G] elements; FP8: [n_bundles][half]
+                       // [lane group][row][32] e4m3 bytes (see kFp8Lane)
   size_t bytes = 0;
 };
+
+// Operand positions of the FP8 bundles (v_mfma_scale_f32_16x16x128_f8f6f4, measured on
+// gfx950): lane (n, g) holds 32 bytes, and the 128 K of one MFMA form four scale blocks of 32.
+// Scale block b consists of the 8-byte slots kFp8Slot[b][i] of lane groups kFp8Lane[b][i]
+// (i < 4), and takes the scale byte of lane group kFp8ScaleLane[b].
+constexpr int kFp8Lane[4][4] = {{0, 0, 1, 1}, {2, 2, 3, 3}, {0, 0, 1, 1}, {2, 2, 3, 3}};
+constexpr int kFp8Slot[4][4] = {{0, 1, 0, 1}, {0, 1, 0, 1}, {2, 3, 2, 3}, {2, 3, 2, 3}};
+constexpr int kFp8ScaleLane[4] = {0, 1, 2, 3};
 
 struct Model {
   aroam_sensor sensor{};
@@ -137,7 +145,8 @@ struct Model {
   long long* d_off = nullptr;    // [n_stored + 1]
   Layout g4f, g4a;               // direct form, G = 4: FP64 forward / adjoint
   Layout s4f, s4a;               // LDS-staged, G = 4: FP32
-  Layout s8f, s8a;               // LDS-staged, G = 8: BF16 / FP8
+  Layout s8f, s8a;               // LDS-staged, G = 8: BF16
+  Layout f8f, f8a;               // LDS-staged, G = 8, bundles of the block-scaled FP8 MFMA
   Pack fwd_pack[4], adj_pack[4]; // indexed by aroam_dtype
   // band-pass filter applied along time to the columns (and, by the caller, to the signals)
   bool filtered = false;
@@ -212,6 +221,30 @@ int server_submit(Server& sv, const Model& m, int kind, const aroam_solve_opts& 
 int server_poll(Server& sv, int* n_resident, int* n_queued);
 int server_collect(Server& sv, int max, long long* ids, aroam_solve_info* infos, int* n);
 void server_destroy(Server* sv);
+
+// FP8 e4m3 code (OCP: sign, 4 exponent bits of bias 7, 3 mantissa bits, largest finite 448,
+// no infinities) of an FP32 value: nearest with ties to even, finite values beyond 448
+// saturate to +-448, and NaN and infinities give the NaN code 0x7f / 0xff.
+__device__ inline uint8_t f32_to_e4m3(float f) {
+  const uint8_t sign = (uint8_t)((__float_as_uint(f) >> 24) & 0x80u);
+  const float a = fabsf(f);
+  if (!(a <= 3.402823466e38f)) return (uint8_t)(sign | 0x7f);
+  if (a >= 448.0f) return (uint8_t)(sign | 0x7e);
+  if (a < 0.015625f) {                     // subnormal range: multiples of 2^-9
+    const float q = rintf(a * 512.0f);     // q = 8 is the smallest normal, code 0x08
+    return (uint8_t)(sign | (uint8_t)q);
+  }
+  int e;
+  const float mant = frexpf(a, &e);        // a = mant 2^e, mant in [0.5, 1)
+  float q = rintf(mant * 16.0f);           // 8..16: implicit bit + 3 fraction bits
+  if (q >= 16.0f) {
+    q = 8.0f;
+    e += 1;
+  }
+  const int eb = e + 6;                    // a = (q / 8) 2^(e - 1), biased exponent e - 1 + 7
+  if (eb > 15 || (eb == 15 && q > 14.0f)) return (uint8_t)(sign | 0x7e);
+  return (uint8_t)(sign | (uint8_t)(eb << 3) | (uint8_t)((int)q - 8));
+}
 
 inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 inline long long round_up(long long a, long long b) { return ceil_div(a, b) * b; }

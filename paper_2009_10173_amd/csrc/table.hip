@@ -240,29 +240,6 @@ __global__ void k_pack(long long total, int G, int TM, bool adjoint,
   }
 }
 
-// FP8 e4m3 (OCP: bias 7, 3 mantissa bits, largest finite 448, no infinities), round to
-// nearest even, saturating at +-448.
-__device__ inline uint8_t f32_to_e4m3(float f) {
-  const uint8_t sign = (uint8_t)((__float_as_uint(f) >> 24) & 0x80u);
-  const float a = fabsf(f);
-  if (!(a == a)) return (uint8_t)(sign | 0x7f);
-  if (a >= 448.0f) return (uint8_t)(sign | 0x7e);
-  if (a < 0.015625f) {                     // subnormal range: multiples of 2^-9
-    const float q = rintf(a * 512.0f);     // q = 8 is the smallest normal, code 0x08
-    return (uint8_t)(sign | (uint8_t)q);
-  }
-  int e;
-  const float mant = frexpf(a, &e);        // a = mant 2^e, mant in [0.5, 1)
-  float q = rintf(mant * 16.0f);           // 8..16: implicit bit + 3 fraction bits
-  if (q >= 16.0f) {
-    q = 8.0f;
-    e += 1;
-  }
-  const int eb = e + 6;                    // a = (q / 8) 2^(e - 1), biased exponent e - 1 + 7
-  if (eb > 15 || (eb == 15 && q > 14.0f)) return (uint8_t)(sign | 0x7e);
-  return (uint8_t)(sign | (uint8_t)(eb << 3) | (uint8_t)((int)q - 8));
-}
-
 // Per (offset, 16-depth block) FP32 scale: the smallest power of two >= amax / 448 of the
 // block's table values (powers of two let the kernel apply the scale inside the FP8 -> BF16
 // conversion).
@@ -289,41 +266,34 @@ __global__ void k_block_scale(int n_off, int nz, const int* __restrict__ colidx,
   scale[id] = sc;
 }
 
-// FP8 pack: entries are e4m3(value / scale) with the scale of the entry's (offset, 16-depth
-// block).  The 16 rows of each half of a K-group lie inside one block (forward: the group's
-// G depths; adjoint: the half's 16 depths), so each (K-group, half) carries one scale
-// (gscale, 0 when the group is empty).
-__global__ void k_pack_fp8(long long total, int G, int TM, bool adjoint,
-                           const int4* __restrict__ groups, int nz, int nt,
-                           const int* __restrict__ colidx, const int* __restrict__ lo,
+// FP8 pack of the block-scaled MFMA layout: entries are e4m3(value / scale) with the scale of
+// the entry's (offset, 16-depth block); K-group q of the layout (operand position order:
+// [bundle][lane group][8-byte slot]) fills, for each 16-row half h and row n, bytes
+// [8 slot, + 8) of lane (n, lane group) in the half's 64 x 32-byte operand.
+__global__ void k_pack_fp8(long long total, bool adjoint, const int4* __restrict__ groups, int nz,
+                           int nt, const int* __restrict__ colidx, const int* __restrict__ lo,
                            const long long* __restrict__ off, const double* __restrict__ band,
-                           const float* __restrict__ bscale, uint8_t* __restrict__ pack,
-                           float* __restrict__ gscale) {
+                           const float* __restrict__ bscale, uint8_t* __restrict__ pack) {
   const int nblk = (nz + 15) / 16;
-  const int NH = TM / 16;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const long long grp = idx / ((long long)TM * G);
-    const int m = (int)((idx / G) % TM);
-    const int j = (int)(idx % G);
-    const int h = m / 16;
-    const int4 gd = groups[grp];
-    // rows past nz (last adjoint tile) hold zeros; their half uses the last block's scale
-    const int kblk = min(nblk - 1, adjoint ? (TM * gd.z) / 16 + h : gd.y / 16);
-    const float sc = gd.x >= 0 ? bscale[(long long)gd.x * nblk + kblk] : 0.0f;
-    if (m % 16 == 0 && j == 0) gscale[grp * NH + h] = sc;
-    int n, k;
-    if (!adjoint) {
-      n = TM * gd.z + m;
-      k = gd.y + j;
-    } else {
-      k = TM * gd.z + m;
-      n = gd.y + j;
+    const long long q = idx / (32 * 8);
+    const int m = (int)((idx / 8) % 32);
+    const int j = (int)(idx % 8);
+    const long long bi = q / 16;
+    const int ln = (int)((q % 16) / 4), slot = (int)(q % 4);
+    const int h = m / 16, n = m % 16;
+    const int4 gd = groups[q];  // (offset index, run start, tile, active)
+    uint8_t code = 0;
+    if (gd.x >= 0) {
+      const int kblk = min(nblk - 1, adjoint ? 2 * gd.z + h : gd.y / 16);
+      const float sc = bscale[(long long)gd.x * nblk + kblk];
+      const int nn = adjoint ? gd.y + j : 32 * gd.z + m;
+      const int k = adjoint ? 32 * gd.z + m : gd.y + j;
+      const double v = table_value(gd.x, nn, k, nz, nt, colidx, lo, off, band);
+      code = f32_to_e4m3((float)(v / sc));
     }
-    const double v = table_value(gd.x, n, k, nz, nt, colidx, lo, off, band);
-    // a lane's entries of both 16-row halves are adjacent: [group][row in half][half][G]
-    const long long pos = grp * TM * G + (long long)((m % 16) * NH + h) * G + j;
-    pack[pos] = sc > 0.0f ? f32_to_e4m3((float)(v / sc)) : (uint8_t)0;
+    pack[((bi * 2 + h) * 64 + ln * 16 + n) * 32 + slot * 8 + j] = code;
   }
 }
 
@@ -714,6 +684,171 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   return plan_pieces(lay, tile_units, chunk_starts, unit_work, 3 * std::max(cus, 1), bytes);
 }
 
+// ---- FP8 layouts: bundles of the block-scaled FP8 MFMA ---------------------------------
+// v_mfma_scale_f32_16x16x128_f8f6f4 multiplies 16 rows by 128 K per 16 positions; lane
+// (n, g) holds 32 bytes of row n (A) or position n (B), and each of the four scale blocks of
+// 32 K takes the scale byte (E8M0, 2^(byte - 127)) of one lane group.  A bundle holds 16
+// K-groups of 8 entries: K-group i of scale block b sits in lane group kFp8Lane[b][i], bytes
+// [8 kFp8Slot[b][i], + 8) of its 32, and lane group kFp8ScaleLane[b] carries block b's scale.
+// The four K-groups of a block share one table scale (and the unit's operand scale).
+bool fp8_key_less(const int4& a, const int4& b) {
+  return a.x != b.x ? a.x < b.x : a.y != b.y ? a.y < b.y : a.z < b.z;
+}
+
+int build_fp8_layout(const Model& m, bool adjoint, const std::vector<float>& bscale, Layout& lay,
+                     size_t& bytes) {
+  const aroam_grid& g = m.grid;
+  const int K = m.K, W = 2 * K + 1, nz = g.nz, nt = g.nt;
+  const int G = 8, TM = kTileRows8, CH = kChunkBytes, BR = kPatchRows, BC = kPatchCols;
+  const int nblk = (int)ceil_div(nz, 16);
+  lay.G = G;
+  lay.TM = TM;
+  lay.staged = true;
+  lay.CH = CH;
+  lay.BR = BR;
+  lay.BC = BC;
+  lay.NCOL = BC + 2 * K;
+  lay.CS = kColumnBytes;  // one byte per entry
+  lay.out_len = adjoint ? nz : nt;
+  lay.n_tiles = (int)ceil_div(lay.out_len, TM);
+  lay.in = pad_geom(g, adjoint ? nt : nz, BR, BC, CH);
+  lay.lds_bytes = (size_t)(BR + 1) * lay.NCOL * lay.CS;
+  AROAM_CHECK((long long)lay.lds_bytes == staged_lds_bytes(K), AROAM_EINVAL,
+              "FP8 layout shape differs from the LDS stage's");
+  const int inner = adjoint ? nt : nz;
+  const int nq = (int)ceil_div(inner, G);
+  const int qpc = CH / G;
+  const int nch = (int)ceil_div(inner, CH);
+  // E8M0 byte of a table block scale (a power of two; 1 for an empty block)
+  auto e8 = [&](int oi, int blk) {
+    int e = 0;
+    std::frexp((double)bscale[(size_t)oi * nblk + std::min(blk, nblk - 1)], &e);
+    return std::max(0, std::min(254, e - 1 + 127));
+  };
+  std::vector<int4> groups, units;  // groups in operand position order: [bundle][lane][slot]
+  std::vector<int2> urows;
+  std::vector<int> rec, bmask, tile_units(lay.n_tiles + 1, 0);
+  std::vector<std::vector<char>> hits(W, std::vector<char>((size_t)nq + 1));
+  std::vector<std::vector<char>> hhits((size_t)W * 2, std::vector<char>((size_t)nq + 1));
+  std::vector<char> dx_any(W);
+  std::vector<std::vector<int>> chunk_starts(lay.n_tiles);
+  std::vector<double> unit_work;
+  struct Entry {
+    int4 group;
+    int off;   // LDS offset of the K-group's run
+    int4 key;  // (half mask, scale byte of half 0, of half 1)
+  };
+  std::vector<std::vector<Entry>> per((size_t)nch * W);
+  const int4 null_group = make_int4(-1, 0, 0, 0);
+  for (int t = 0; t < lay.n_tiles; ++t) {
+    tile_units[t] = (int)units.size();
+    for (auto& v : per) v.clear();
+    for (int a = 0; a < W; ++a) {
+      const int slot_r = adjoint ? (W - 1 - a) : a;
+      for (int b = 0; b < W; ++b) {
+        dx_any[b] = tile_hits(m, adjoint, G, TM, t, a * W + b, hits[b]);
+        if (dx_any[b])
+          for (int h = 0; h < 2; ++h)
+            tile_hits(m, adjoint, G, kTile, 2 * t + h, a * W + b, hhits[(size_t)b * 2 + h]);
+      }
+      for (int b = 0; b < W; ++b) {
+        if (!dx_any[b]) continue;
+        const int col = adjoint ? (W - 1 - b) : b;
+        const int oi = a * W + b;
+        for (int q = 0; q < nq; ++q) {
+          if (!hits[b][q]) continue;
+          const int c = q / qpc;
+          const int mask = (hhits[(size_t)b * 2][q] ? 1 : 0) | (hhits[(size_t)b * 2 + 1][q] ? 2 : 0);
+          const int s0 = adjoint ? e8(oi, 2 * t) : e8(oi, (q * G) / 16);
+          const int s1 = adjoint ? e8(oi, 2 * t + 1) : s0;
+          per[(size_t)c * W + slot_r].push_back(
+              Entry{make_int4(oi, q * G, t, 1), col * lay.CS + (q % qpc) * G,
+                    make_int4(mask, s0, s1, 0)});
+        }
+      }
+    }
+    for (int c = 0; c < nch; ++c) {
+      int prevR = -1;
+      for (int R = 0; R < W; ++R) {
+        auto& lst = per[(size_t)c * W + R];
+        if (lst.empty()) continue;
+        if (prevR < 0) chunk_starts[t].push_back((int)units.size());
+        const int first_bundle = (int)(groups.size() / 16);
+        // scale blocks: K-groups of equal key, four at a time (a short block is padded with
+        // null K-groups, whose table entries are zero)
+        std::stable_sort(lst.begin(), lst.end(),
+                         [](const Entry& x, const Entry& y) { return fp8_key_less(x.key, y.key); });
+        std::vector<std::vector<Entry>> blocks;
+        for (size_t i = 0; i < lst.size();) {
+          size_t j = i;
+          std::vector<Entry> blk;
+          while (j < lst.size() && blk.size() < 4 && !fp8_key_less(lst[i].key, lst[j].key) &&
+                 !fp8_key_less(lst[j].key, lst[i].key))
+            blk.push_back(lst[j++]);
+          while (blk.size() < 4) blk.push_back(Entry{null_group, 0, lst[i].key});
+          blocks.push_back(blk);
+          i = j;
+        }
+        // bundles: four blocks of one half mask (blocks are sorted by mask first)
+        for (size_t i = 0; i < blocks.size();) {
+          const int mask = blocks[i][0].key.x;
+          std::vector<std::vector<Entry>> bun;
+          while (i < blocks.size() && bun.size() < 4 && blocks[i][0].key.x == mask)
+            bun.push_back(blocks[i++]);
+          while (bun.size() < 4)
+            bun.push_back(std::vector<Entry>(4, Entry{null_group, 0, make_int4(mask, 127, 127, 0)}));
+          const size_t base = groups.size();
+          groups.resize(base + 16, null_group);
+          std::vector<int> off(16, 0), sc(4, 0);
+          for (int bb = 0; bb < 4; ++bb) {
+            for (int k = 0; k < 4; ++k) {
+              const int pos = kFp8Lane[bb][k] * 4 + kFp8Slot[bb][k];
+              groups[base + pos] = bun[bb][k].group;
+              if (groups[base + pos].x >= 0) groups[base + pos].z = t;
+              off[pos] = bun[bb][k].off;
+            }
+            sc[kFp8ScaleLane[bb]] = bun[bb][0].key.y | (bun[bb][0].key.z << 8);
+          }
+          for (int ln = 0; ln < 4; ++ln) {
+            rec.push_back(off[4 * ln] | (off[4 * ln + 1] << 16));
+            rec.push_back(off[4 * ln + 2] | (off[4 * ln + 3] << 16));
+            rec.push_back(sc[ln]);
+            rec.push_back(ln == 0 ? mask : 0);
+          }
+          bmask.push_back(mask);
+        }
+        const int lo = (prevR < 0 || R >= prevR + BR) ? R : prevR + BR;
+        const int nb = (int)(groups.size() / 16);
+        units.push_back(make_int4(R - K, c * CH, first_bundle, nb));
+        urows.push_back(make_int2(lo, R + BR));
+        double w = 0;
+        for (int bi = first_bundle; bi < nb; ++bi) w += __builtin_popcount((unsigned)bmask[bi]);
+        unit_work.push_back(w);
+        prevR = R;
+      }
+    }
+  }
+  tile_units[lay.n_tiles] = (int)units.size();
+  lay.n_units = (long long)units.size();
+  lay.n_bundles = (long long)groups.size() / 16;
+  long long halves = 0;
+  for (int bm : bmask) halves += __builtin_popcount((unsigned)bm);
+  lay.mac_exec = halves * 16LL * kTile * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
+  AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
+              "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
+  AROAM_CHECK(lay.NCOL * lay.CS < 65536, AROAM_EINVAL, "LDS offsets exceed 16 bits");
+  AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_ucols, urows, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_meta, rec, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_bmask, bmask, bytes));
+  AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
+  lay.h_tile_start = tile_units;
+  lay.n_patches = (int)(ceil_div(g.ny, BR) * ceil_div(g.nx, BC));
+  int cus = 0;
+  AROAM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m.device));
+  return plan_pieces(lay, tile_units, chunk_starts, unit_work, 3 * std::max(cus, 1), bytes);
+}
+
 template <typename T>
 int pack_dtype(const Model& m, const Layout& lay, bool adjoint, Pack& p, hipStream_t st,
                size_t& bytes) {
@@ -733,24 +868,22 @@ int pack_dtype(const Model& m, const Layout& lay, bool adjoint, Pack& p, hipStre
 
 int pack_fp8(const Model& m, const Layout& lay, bool adjoint, const float* bscale, Pack& p,
              hipStream_t st, size_t& bytes) {
-  const long long n_groups = lay.n_bundles * kLaneGroups;
-  const long long n_scales = n_groups * (lay.TM / 16);
-  const long long total = n_groups * lay.TM * lay.G;
+  const long long total = lay.n_bundles * 16 * 32 * 8;
   p.bytes = std::max<long long>(1, total);
   AROAM_HIP(hipMalloc(&p.d, p.bytes));
-  AROAM_HIP(hipMalloc((void**)&p.d_scale, std::max<long long>(1, n_scales) * sizeof(float)));
-  p.bytes += std::max<long long>(1, n_scales) * sizeof(float);
   bytes += p.bytes;
   if (total > 0) {
     const int blocks = (int)std::min<long long>(ceil_div(total, 256), 1 << 16);
-    hipLaunchKernelGGL(k_pack_fp8, dim3(blocks), dim3(256), 0, st, total, lay.G, lay.TM, adjoint,
-                       lay.d_groups, m.grid.nz, m.grid.nt, m.d_colidx, m.d_lo, m.d_off, m.d_band,
-                       bscale, (uint8_t*)p.d, p.d_scale);
+    hipLaunchKernelGGL(k_pack_fp8, dim3(blocks), dim3(256), 0, st, total, adjoint, lay.d_groups,
+                       m.grid.nz, m.grid.nt, m.d_colidx, m.d_lo, m.d_off, m.d_band, bscale,
+                       (uint8_t*)p.d);
     AROAM_HIP(hipGetLastError());
   }
   return AROAM_OK;
 }
 
+// Block scales on the device, their copy on the host (the layout groups K-groups by scale),
+// the FP8 layouts of both directions, and their packs.
 int pack_all_fp8(Model& m, hipStream_t st, size_t& bytes) {
   const int nblk = (int)ceil_div(m.grid.nz, 16);
   float* bscale = nullptr;
@@ -759,8 +892,15 @@ int pack_all_fp8(Model& m, hipStream_t st, size_t& bytes) {
   hipLaunchKernelGGL(k_block_scale, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, st, m.n_off,
                      m.grid.nz, m.d_colidx, m.d_off, m.d_band, bscale);
   int rc = hipGetLastError() == hipSuccess ? AROAM_OK : AROAM_EDEVICE;
-  if (!rc) rc = pack_fp8(m, m.s8f, false, bscale, m.fwd_pack[AROAM_FP8E4M3], st, bytes);
-  if (!rc) rc = pack_fp8(m, m.s8a, true, bscale, m.adj_pack[AROAM_FP8E4M3], st, bytes);
+  std::vector<float> h_scale((size_t)std::max<long long>(1, nb));
+  if (!rc && (hipMemcpyAsync(h_scale.data(), bscale, nb * sizeof(float), hipMemcpyDeviceToHost,
+                             st) != hipSuccess ||
+              hipStreamSynchronize(st) != hipSuccess))
+    rc = AROAM_EDEVICE;
+  if (!rc) rc = build_fp8_layout(m, false, h_scale, m.f8f, bytes);
+  if (!rc) rc = build_fp8_layout(m, true, h_scale, m.f8a, bytes);
+  if (!rc) rc = pack_fp8(m, m.f8f, false, bscale, m.fwd_pack[AROAM_FP8E4M3], st, bytes);
+  if (!rc) rc = pack_fp8(m, m.f8a, true, bscale, m.adj_pack[AROAM_FP8E4M3], st, bytes);
   if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = AROAM_EDEVICE;
   (void)hipFree(bscale);
   if (rc) set_error("FP8 packing failed");
@@ -1146,16 +1286,20 @@ int export_quantized(const Model& m, int dtype, bool adjoint, double* dense, flo
               dtype);
   const Layout& lay = layout_for(m, adjoint, dtype);
   const Pack& pk = adjoint ? m.adj_pack[dtype] : m.fwd_pack[dtype];
-  const int nz = m.grid.nz, nt = m.grid.nt, TM = lay.TM, G = lay.G, NH = TM / kTile;
+  const int nz = m.grid.nz, nt = m.grid.nt, TM = lay.TM, G = lay.G;
   const int nblk = (int)ceil_div(nz, 16);
-  const size_t n_groups = (size_t)lay.n_bundles * kLaneGroups;
+  const bool fp8 = dtype == AROAM_FP8E4M3;
+  const size_t n_groups = (size_t)lay.n_bundles * (fp8 ? 16 : kLaneGroups);
   std::vector<int4> groups;
   AROAM_TRY(download(groups, lay.d_groups, n_groups));
   const size_t esize = dtype == AROAM_FP32 ? 4 : dtype == AROAM_BF16 ? 2 : 1;
   std::vector<uint8_t> raw;
   AROAM_TRY(download(raw, pk.d, n_groups * TM * G * esize));
-  std::vector<float> gscale;
-  if (dtype == AROAM_FP8E4M3) AROAM_TRY(download(gscale, pk.d_scale, n_groups * NH));
+  std::vector<int> rec;
+  if (fp8) AROAM_TRY(download(rec, lay.d_meta, (size_t)lay.n_bundles * 16));
+  int block_of[4][4];  // scale block of (lane group, slot) in an FP8 bundle
+  for (int b = 0; b < 4; ++b)
+    for (int i = 0; i < 4; ++i) block_of[kFp8Lane[b][i]][kFp8Slot[b][i]] = b;
   std::fill(dense, dense + (size_t)m.n_off * nz * nt, 0.0);
   if (scales) std::fill(scales, scales + (size_t)m.n_off * nblk, 0.0f);
   for (size_t q = 0; q < n_groups; ++q) {
@@ -1166,26 +1310,30 @@ int export_quantized(const Model& m, int dtype, bool adjoint, double* dense, flo
         const int n = adjoint ? gd.y + j : TM * gd.z + r;
         const int k = adjoint ? TM * gd.z + r : gd.y + j;
         if (n >= nt || k >= nz) continue;
-        const size_t e = q * TM * G + (size_t)r * G + j;
         double v;
         if (dtype == AROAM_FP32) {
           float f;
-          std::memcpy(&f, &raw[4 * e], 4);
+          std::memcpy(&f, &raw[4 * (q * TM * G + (size_t)r * G + j)], 4);
           v = f;
         } else if (dtype == AROAM_BF16) {
+          const size_t e = q * TM * G + (size_t)r * G + j;
           const uint32_t bits = (uint32_t)(raw[2 * e] | (raw[2 * e + 1] << 8)) << 16;
           float f;
           std::memcpy(&f, &bits, 4);
           v = f;
         } else {
-          // a lane's entries of both halves are adjacent: [group][row in half][half][G]
-          const int h = r / kTile;
-          const size_t pos = q * TM * G + (size_t)((r % kTile) * NH + h) * G + j;
-          const float sc = gscale[q * NH + h];
-          v = e4m3_value(raw[pos]) * (double)sc;
+          // K-group q = [bundle][lane group][slot]; its scale is the E8M0 byte of the half in
+          // the record word of the lane group that carries its block's scale
+          const size_t bi = q / 16;
+          const int ln = (int)((q % 16) / 4), slot = (int)(q % 4), h = r / kTile;
+          const size_t pos = ((bi * 2 + h) * 64 + ln * 16 + r % kTile) * 32 + slot * 8 + j;
+          const int sl = kFp8ScaleLane[block_of[ln][slot]];
+          const int e8 = (rec[bi * 16 + sl * 4 + 2] >> (8 * h)) & 0xff;
+          const double sc = std::ldexp(1.0, e8 - 127);
+          v = e4m3_value(raw[pos]) * sc;
           // a block with entries has a nonzero code (its largest lands in the top binade);
           // the scale a pack carries for an empty block is not reported
-          if (scales && v != 0.0) scales[(size_t)gd.x * nblk + k / 16] = sc;
+          if (scales && v != 0.0) scales[(size_t)gd.x * nblk + k / 16] = (float)sc;
         }
         dense[((size_t)gd.x * nz + k) * nt + n] = v;
       }
@@ -1264,7 +1412,7 @@ int import_model(const aroam_grid* g, const double* dense, const int* col_lo,
 // table and FP64 / FP32 packs are built (rc: status of that stage).
 int finish_model(Model* m, int rc, unsigned mask, hipStream_t st, Model** out) {
   if (rc == AROAM_OK) {
-    const bool want8 = (mask & ((1u << AROAM_BF16) | (1u << AROAM_FP8E4M3))) != 0;
+    const bool want8 = (mask & (1u << AROAM_BF16)) != 0;
     size_t bytes = 0;
     if (want8) {
       rc = build_staged_layout(*m, false, 8, kTileRows8, 32, kPatchRows, kPatchCols, 2, m->s8f,
@@ -1294,8 +1442,8 @@ int finish_model(Model* m, int rc, unsigned mask, hipStream_t st, Model** out) {
   // account device memory
   size_t b = (size_t)std::max<long long>(1, m->nnz_stored) * sizeof(double);
   b += m->h_colidx.size() * sizeof(int) + m->n_stored * sizeof(int) + m->h_off.size() * 8;
-  for (const Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a})
-    b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) +
+  for (const Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a, &m->f8f, &m->f8a})
+    b += l->n_bundles * kLaneGroups * (sizeof(int) + sizeof(int4)) * (l == &m->f8f || l == &m->f8a ? 4 : 1) +
          (l->staged ? l->n_bundles * sizeof(int) + l->n_pieces * sizeof(int4) +
                           l->n_tiles * sizeof(int2)
                     : l->h_tile_start.size() * sizeof(int)) +
@@ -1315,7 +1463,7 @@ void destroy_model(Model* m) {
   (void)hipFree(m->d_colidx);
   (void)hipFree(m->d_lo);
   (void)hipFree(m->d_off);
-  for (Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a}) {
+  for (Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a, &m->f8f, &m->f8a}) {
     (void)hipFree(l->d_tile_start);
     (void)hipFree(l->d_meta);
     (void)hipFree(l->d_bmask);
@@ -1327,9 +1475,7 @@ void destroy_model(Model* m) {
   }
   for (int d = 0; d < 4; ++d) {
     (void)hipFree(m->fwd_pack[d].d);
-    (void)hipFree(m->fwd_pack[d].d_scale);
     (void)hipFree(m->adj_pack[d].d);
-    (void)hipFree(m->adj_pack[d].d_scale);
   }
   delete m;
 }

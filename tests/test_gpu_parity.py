@@ -198,8 +198,9 @@ def test_full_size_fine_step_windows(dtype, tol):
     """Full-size 400x400 scan at 5 um, 256 depths, Nt 1024, cone capped at 81x81 offsets, in
     the launch configuration the bench times.  The oracle evaluates 64x64 windows (interior
     and corner) on two depth slabs: one capped by the 81x81 box, one at the focus.  FP32 is
-    held to the apply tolerance; FP8 (e4m3 table, BF16 vectors) is reported with the bound
-    of the small FP8 tests."""
+    held to the apply tolerance; FP8 (e4m3 table and operand) is reported with the bound
+    of the small FP8 tests (its element-wise check against the quantised reference is in
+    tests/test_gpu_quantized.py)."""
     name = "vessels400"
     cfg = W.config(name)
     g = cfg["grid"]
@@ -458,10 +459,11 @@ def test_fista_fp8_anchored_matches_oracle(name, period, warmup):
 
 @pytest.mark.parametrize("name", SMALL)
 def test_forward_adjoint_fp8_reported(name):
-    """e4m3 table with one FP32 scale per (offset, 16-depth block), BF16 vector operands, FP32
-    accumulation: error vs the FP64 oracle is reported.  e4m3 keeps 3 mantissa bits, so an
-    entry carries up to 2^-4 = 6.25 % rounding error (entries far below their block's maximum
-    fall into the subnormal range and carry more); the bound is 1e-1."""
+    """e4m3 table with one power-of-two scale per (offset, 16-depth block), e4m3 operands with
+    one per 64 entries of the fast axis, block-scaled FP8 MFMA, FP32 accumulation: error vs the
+    FP64 oracle is reported.  e4m3 keeps 3 mantissa bits, so an entry carries up to 2^-4 =
+    6.25 % rounding error (entries far below their block's maximum fall into the subnormal
+    range and carry more); the bound is 1e-1."""
     cfg = W.config(name)
     m = gpu_model(name)
     H = oracle_table(name)

@@ -10,8 +10,13 @@ output (one quantisation step times the operand) widens that output's bound.  Ev
 entry must match exactly.
 
 Element-wise bound of the applies: 1e-5 of the largest output entry (the FP32 accumulation of
-exact products, as for the FP32 apply) plus the ambiguity term.  The error of each apply
-against the unquantised FP64 oracle is reported beside it (the figures the precision
+exact products, as for the FP32 apply) plus the ambiguity term.  The FP8 apply runs on the
+block-scaled FP8 MFMA, which adds up each 128-term product with less than FP32 precision:
+measured on gfx950 over 768 random dot products of normal e4m3 codes, its error stays below
+8.7e-5 of the sum of the absolute products.  Its bound therefore adds 2^-13 (1.2e-4) times
+the output's sum of absolute products, |Hq| |xq| (every MFMA's error is bounded by its share
+of that sum, and the FP32 accumulation of the MFMA results adds to them).  The error of each
+apply against the unquantised FP64 oracle is reported beside it (the figures the precision
 discussion uses); the bounds of those reports stay in tests/test_gpu_parity.py."""
 import functools
 
@@ -31,8 +36,9 @@ import paper_2009_10173_amd as P  # noqa: E402
 
 SMALL = ["tiny", "mid", "mid7"]
 # operand quantisation of each reduced-precision apply
-OPERAND = {"bf16": "bf16", "fp8": "bf16"}
+OPERAND = {"bf16": "bf16", "fp8": "fp8-operand"}
 TOL = 1e-5
+FP8_MFMA_SUM = 2.0 ** -13  # relative accuracy of the FP8 MFMA's sums (see the docstring)
 
 _MODELS = {}
 
@@ -94,12 +100,14 @@ def test_packed_table_matches_oracle_quantisation(name, dtype, adjoint):
         assert np.array_equal(sc[~blk_amb], sc_ref[~blk_amb].astype(np.float32))
 
 
-def _bound(op, lo, hi, v):
-    """Largest change of op(Hq, v) that the ambiguous entries can make."""
+def _bound(op, lo, hi, v, dtype, Hq):
+    """Largest change of op(Hq, v) that the ambiguous entries can make, plus, for FP8, the
+    accuracy of the FP8 MFMA's sums times the output's sum of absolute products."""
     d = hi - lo
-    if not np.any(d):
-        return 0.0
-    return op(d, np.abs(v))
+    b = op(d, np.abs(v)) if np.any(d) else 0.0
+    if dtype == "fp8":
+        b = b + FP8_MFMA_SUM * op(np.abs(Hq), np.abs(v))
+    return b
 
 
 def check_apply(got, ref, bound, label, oracle_err):
@@ -126,10 +134,10 @@ def test_quantized_applies_match_reference_elementwise(name, dtype):
     xa = m.adjoint(t32(y), dtype).cpu().numpy()
     s_ref = oops.forward(Hq, xq)
     xa_ref = oops.adjoint(Hq, yq)
-    check_apply(s, s_ref, _bound(oops.forward, lo, hi, xq), f"{name} {dtype} forward",
-                rel_l2(s, oops.forward(H, x)))
-    check_apply(xa, xa_ref, _bound(oops.adjoint, lo, hi, yq), f"{name} {dtype} adjoint",
-                rel_l2(xa, oops.adjoint(H, y)))
+    check_apply(s, s_ref, _bound(oops.forward, lo, hi, xq, dtype, Hq),
+                f"{name} {dtype} forward", rel_l2(s, oops.forward(H, x)))
+    check_apply(xa, xa_ref, _bound(oops.adjoint, lo, hi, yq, dtype, Hq),
+                f"{name} {dtype} adjoint", rel_l2(xa, oops.adjoint(H, y)))
 
 
 @functools.lru_cache(maxsize=None)
@@ -139,6 +147,14 @@ def window400_blocks():
     cfg = W.config("vessels400")
     ks = list(range(16, 32)) + list(range(128, 144))
     return ks, omodel.build_depth_slabs(cfg["sensor"], cfg["grid"], ks)
+
+
+def _window_bound(op, lo, hi, Hq, v, dtype, y0, x0):
+    """`_bound` of a 64 x 64 window of the full grid (the operators reach K offsets)."""
+    b = window_apply(op, hi - lo, np.abs(v), y0, x0, 64)
+    if dtype == "fp8":
+        b = b + FP8_MFMA_SUM * window_apply(op, np.abs(Hq), np.abs(v), y0, x0, 64)
+    return b
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
@@ -166,9 +182,9 @@ def test_full_size_fine_step_windows_quantized(dtype):
     Hq2, lo2, hi2 = Hq[:, :, pick], lo[:, :, pick], hi[:, :, pick]
     for y0, x0 in ((170, 203), (0, 336)):
         s_ref = window_apply(oops.forward, Hq2, xq, y0, x0, 64)
-        b_f = window_apply(oops.forward, hi2 - lo2, np.abs(xq), y0, x0, 64)
+        b_f = _window_bound(oops.forward, lo2, hi2, Hq2, xq, dtype, y0, x0)
         xa_ref = window_apply(oops.adjoint, Hq2, yq, y0, x0, 64)
-        b_a = window_apply(oops.adjoint, hi2 - lo2, np.abs(yq), y0, x0, 64)
+        b_a = _window_bound(oops.adjoint, lo2, hi2, Hq2, yq, dtype, y0, x0)
         check_apply(s[y0:y0 + 64, x0:x0 + 64], s_ref, b_f, f"window400 {dtype} forward ({y0},{x0})",
                     rel_l2(s[y0:y0 + 64, x0:x0 + 64],
                            window_apply(oops.forward, Hs[:, :, pick], x[:, :, [30, 128]].astype(

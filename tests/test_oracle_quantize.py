@@ -157,14 +157,19 @@ def test_ambiguity_marks_planted_fp8_scale_boundary():
 
 def test_fp8_operand_scales_per_block_of_the_fast_axis():
     rng = np.random.default_rng(5)
-    v = rng.standard_normal((3, 4, 37)).astype(np.float32)
-    v[..., 16:32] *= 1e-3
-    sc = Q.operand_scales(v, 37)
-    assert sc.shape == (3,)
-    for b in range(3):
-        amax = np.max(np.abs(v[..., 16 * b:16 * (b + 1)]))
+    v = rng.standard_normal((3, 4, 150)).astype(np.float32)
+    v[..., 64:128] *= 1e-3
+    v[..., 128:] = 0.0
+    sc = Q.operand_scales(v, 150)
+    assert sc.shape == (3,) and sc[2] == 0.0
+    for b in range(2):
+        amax = np.max(np.abs(v[..., 64 * b:64 * (b + 1)]))
         assert sc[b] >= amax / 448 > sc[b] / 2
     q = Q.quantize_operand(v, "fp8-operand")
-    rel = np.abs(q - v) / np.repeat(sc, 16)[:37]
-    assert np.all(rel <= 16.0)                      # half a step of the top binade [256, 448]
-    assert np.all(np.abs(q - v) <= np.abs(v) * 2.0 ** -4 + np.repeat(sc, 16)[:37] * 2.0 ** -10)
+    s = np.repeat(sc, 64)[:150]
+    assert np.all(q[..., 128:] == 0.0)
+    s1 = np.where(s > 0, s, 1.0)
+    assert np.all(np.abs(q - v) / s1 <= 16.0)        # half a step of the top binade [256, 448]
+    assert np.all(np.abs(q - v) <= np.abs(v) * 2.0 ** -4 + s * 2.0 ** -10)
+    # codes of the scaled values are e4m3 codes: decoding q / s gives back exactly q / s
+    assert np.array_equal(Q.e4m3(q / s1), q / s1)
