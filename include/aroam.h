@@ -228,6 +228,20 @@ int aroam_model_export_quantized(const aroam_model* model, int dtype, int adjoin
  * Errors: AROAM_EINVAL, AROAM_EUNSUPPORTED (dtype not packed), AROAM_ENOMEM, AROAM_EDEVICE. */
 int aroam_forward(const aroam_model* model, int dtype, const void* x, void* s, void* stream);
 
+/* aroam_forward that allocates nothing, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation).  The same
+ * kernels and result as aroam_forward (bit for bit), but the apply's scratch (the zero-padded
+ * staged input and the partial sums of cut tiles) lives in a static device array of 64 MiB
+ * that the library holds on each GPU it runs on until the process ends, instead of coming from
+ * the memory pool.  Every call on one GPU shares that array: calls that overlap on one GPU
+ * (on different streams, or from different threads) race and give undefined results;
+ * serialise them.  The array needs no clearing: each call writes all of it that it reads.
+ * Errors: as aroam_forward, plus AROAM_EINVAL when the apply needs more than the 64 MiB
+ * (the message gives the size; the 200x200 workload's forward needs 33 MB, a 400x400 one
+ * with 256 depths about 0.25 GB). */
+int aroam_forward_noalloc(const aroam_model* model, int dtype, const void* x, void* s,
+                          void* stream);
+
 /* x = A^T s:  x[jy, jx, k] = sum_{o, (jy-dy, jx-dx) in grid} sum_n H[o][n, k] s[jy-dy, jx-dx, n].
  * Every element of x is written.  Same errors as aroam_forward. */
 int aroam_adjoint(const aroam_model* model, int dtype, const void* s, void* x, void* stream);

@@ -6,7 +6,7 @@ marshals arguments to it.  See `include/aroam.h` for the ABI.
 from .binding import (  # noqa: F401
     AROAM_BF16, AROAM_FP32, AROAM_FP64, AROAM_FP8E4M3, DTYPES, AroamError, Model, aroam_adjoint,
     aroam_adjoint_batch, aroam_build_model, aroam_build_model_filtered, aroam_filter_signals,
-    aroam_forward, aroam_forward_batch, aroam_import_model,
+    aroam_forward, aroam_forward_batch, aroam_forward_noalloc, aroam_import_model,
     aroam_last_error, aroam_model_destroy, aroam_model_export_quantized, aroam_model_export_table,
     aroam_model_query,
     aroam_server_collect, aroam_server_create, aroam_server_destroy, aroam_server_poll,

@@ -78,6 +78,8 @@ _SYMBOLS = {
     "aroam_model_export_quantized": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p],
                                      C.c_int),
     "aroam_forward": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "aroam_forward_noalloc": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
+                              C.c_int),
     "aroam_adjoint": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "aroam_solve_lsqr": ([C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                           C.POINTER(SolveInfo), C.c_void_p], C.c_int),
@@ -257,6 +259,10 @@ def aroam_model_export_quantized(h, grid, dtype, adjoint=False):
 
 def aroam_forward(h, dtype, x, s, stream=None):
     _check(load_library().aroam_forward(h, dtype, _ptr(x), _ptr(s), _stream(stream)))
+
+
+def aroam_forward_noalloc(h, dtype, x, s, stream=None):
+    _check(load_library().aroam_forward_noalloc(h, dtype, _ptr(x), _ptr(s), _stream(stream)))
 
 
 def aroam_adjoint(h, dtype, s, x, stream=None):

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <mutex>
 
 #include "internal.h"
 
@@ -969,6 +970,53 @@ int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, vo
   if (rc != AROAM_OK) return rc;
   AROAM_CHECK(e == hipSuccess, AROAM_EDEVICE, "hipFreeAsync failed: %s", hipGetErrorString(e));
   return AROAM_OK;
+}
+
+// Stage buffer of the allocation-free applies: a static device array, one copy per GPU the
+// library runs on, held until the process ends.  In host code `scratch` names a host-side
+// stand-in, so its device address is looked up once per device and only that address is
+// passed to kernels.
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+int static_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  AROAM_HIP(hipGetDevice(&dev));
+  AROAM_CHECK(dev >= 0 && dev < kMaxDevices, AROAM_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    AROAM_CHECK(e == hipSuccess && p, AROAM_EDEVICE,
+                "hipGetSymbolAddress of the static scratch buffer failed: %s", hipGetErrorString(e));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return AROAM_OK;
+}
+
+}  // namespace
+
+int apply_noalloc(const Model& m, bool adjoint, int dtype, const void* in, void* out,
+                  hipStream_t st) {
+  AROAM_CHECK(dtype >= AROAM_FP64 && dtype <= AROAM_FP8E4M3, AROAM_EINVAL, "bad dtype %d", dtype);
+  AROAM_CHECK(in && out, AROAM_EINVAL, "NULL vector");
+  AROAM_CHECK((m.dtype_mask >> dtype) & 1u, AROAM_EUNSUPPORTED,
+              "model was not packed for dtype %d", dtype);
+  const Layout& lay = layout_for(m, adjoint, dtype);
+  AROAM_CHECK(!lay.staged || lay.lds_bytes <= kLdsBytes, AROAM_EINVAL,
+              "lateral footprint too wide for the LDS stage (%zu bytes)", lay.lds_bytes);
+  const size_t need = stage_bytes(m, adjoint, dtype);
+  AROAM_CHECK(need <= kStaticScratchBytes, AROAM_EINVAL,
+              "the apply needs %zu bytes of scratch; the static buffer holds %zu", need,
+              (size_t)kStaticScratchBytes);
+  void* buf = nullptr;
+  AROAM_TRY(static_scratch(&buf));
+  return launch_apply(m, adjoint, dtype, in, out, buf, st);
 }
 
 int apply_batch(int n, const Model* const* ms, bool adjoint, int dtype, const float* const* in,

@@ -219,6 +219,16 @@ int aroam_forward(const aroam_model* model, int dtype, const void* x, void* s, v
   return aroam::apply(*model->m, false, dtype, x, s, nullptr, (hipStream_t)stream);
 }
 
+int aroam_forward_noalloc(const aroam_model* model, int dtype, const void* x, void* s,
+                          void* stream) {
+  aroam::clear_error();
+  if (!model) {
+    aroam::set_error("NULL model");
+    return AROAM_EINVAL;
+  }
+  return aroam::apply_noalloc(*model->m, false, dtype, x, s, (hipStream_t)stream);
+}
+
 int aroam_adjoint(const aroam_model* model, int dtype, const void* s, void* x, void* stream) {
   aroam::clear_error();
   if (!model) {

@@ -189,6 +189,11 @@ size_t stage_bytes(const Model& m, bool adjoint, int dtype);
 // stage_bytes() bytes that the call may overwrite.
 int apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* stage,
           hipStream_t st);
+// apply() with its stage buffer in a static device array of kStaticScratchBytes (no
+// allocation); calls that overlap on one device race for that array.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+int apply_noalloc(const Model& m, bool adjoint, int dtype, const void* in, void* out,
+                  hipStream_t st);
 // Ragged batch of FP32-vector applies (dtype FP32, BF16 or FP8): the single applies of the
 // requests, enqueued in index order on one stream.
 int apply_batch(int n, const Model* const* ms, bool adjoint, int dtype, const float* const* in,
