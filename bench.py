@@ -292,6 +292,8 @@ def main():
                          "reconstruction with one core and with all cores (minutes more)")
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests in the serving leg (0 skips it)")
+    ap.add_argument("--no-recon", action="store_true",
+                    help="skip the full and refined reconstructions (for profiler passes)")
     ap.add_argument("--serve-modes", default="fifo_fp32,served_bf16r")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0,
                     help="device-memory budget of the scheduler's admission (GiB)")
@@ -367,14 +369,21 @@ def main():
     }
     # the full reconstruction in the plain precision, then reduced precision with two FP32
     # residual-correction sweeps
-    (x32, _), t_rec = timed(lambda: model.solve_lsqr(s, lam=-1.0, iters=iters, inner=args.dtype))
-    log(f"{args.dtype} reconstruction ({iters} iterations): {t_rec:.2f} s")
-    result["recon"] = {"iters": iters, "dtype": args.dtype, "recon_ms": t_rec * 1e3,
-                       "pairs_per_s": (iters + 0.5) / t_rec}
+    x32 = None
+    if not args.no_recon:
+        (x32, _), t_rec = timed(lambda: model.solve_lsqr(s, lam=-1.0, iters=iters,
+                                                         inner=args.dtype))
+        log(f"{args.dtype} reconstruction ({iters} iterations): {t_rec:.2f} s")
+        result["recon"] = {"iters": iters, "dtype": args.dtype, "recon_ms": t_rec * 1e3,
+                           "pairs_per_s": (iters + 0.5) / t_rec}
     for lo in lows:
         if lo == args.dtype:
             continue
         kt_lo = kernel_times(model, lo, x0, s, args.kernel_reps)
+        log(f"kernel times {lo}: {kt_lo}")
+        if args.no_recon:
+            result[f"{lo}_kernel_ms"] = kt_lo
+            continue
         (xr, rinfo), t_ref = timed(lambda: model.solve_lsqr(
             s, lam=-1.0, iters=iters, inner=lo, outer=args.dtype, refine_sweeps=2))
         diff = ((xr - x32).norm() / x32.norm()).item()

@@ -775,18 +775,38 @@ int build_fp8_layout(const Model& m, bool adjoint, const std::vector<float>& bsc
         if (prevR < 0) chunk_starts[t].push_back((int)units.size());
         const int first_bundle = (int)(groups.size() / 16);
         // scale blocks: K-groups of equal key, four at a time (a short block is padded with
-        // null K-groups, whose table entries are zero)
+        // null K-groups, whose table entries are zero).  A block's K-groups 0, 1 and 2, 3 sit
+        // in two lane groups at the same two 8-byte slots, and the 32 lanes of a pass of an
+        // 8-byte LDS read hit distinct banks only when those two lane groups' runs (8-byte
+        // steps within a column of 80 bytes) differ in parity: a block takes two K-groups of
+        // even and two of odd run where the class has them, evens first.
         std::stable_sort(lst.begin(), lst.end(),
                          [](const Entry& x, const Entry& y) { return fp8_key_less(x.key, y.key); });
         std::vector<std::vector<Entry>> blocks;
         for (size_t i = 0; i < lst.size();) {
           size_t j = i;
-          std::vector<Entry> blk;
-          while (j < lst.size() && blk.size() < 4 && !fp8_key_less(lst[i].key, lst[j].key) &&
-                 !fp8_key_less(lst[j].key, lst[i].key))
-            blk.push_back(lst[j++]);
-          while (blk.size() < 4) blk.push_back(Entry{null_group, 0, lst[i].key});
-          blocks.push_back(blk);
+          std::vector<Entry> ev, od;
+          while (j < lst.size() && !fp8_key_less(lst[i].key, lst[j].key) &&
+                 !fp8_key_less(lst[j].key, lst[i].key)) {
+            ((lst[j].off / G) % 2 ? od : ev).push_back(lst[j]);
+            ++j;
+          }
+          const Entry null_even{null_group, 0, lst[i].key}, null_odd{null_group, G, lst[i].key};
+          size_t a = 0, b = 0;
+          while (a < ev.size() || b < od.size()) {
+            std::vector<Entry> blk;
+            // two evens then two odds when both are left, else four of what is left
+            const bool both = ev.size() - a >= 2 && od.size() - b >= 2;
+            for (int k = 0; k < 4; ++k) {
+              const bool want_even = both ? k < 2 : (a < ev.size());
+              if (want_even && a < ev.size()) blk.push_back(ev[a++]);
+              else if (!want_even && b < od.size()) blk.push_back(od[b++]);
+              else if (a < ev.size()) blk.push_back(ev[a++]);
+              else if (b < od.size()) blk.push_back(od[b++]);
+              else blk.push_back(k < 2 ? null_even : null_odd);
+            }
+            blocks.push_back(blk);
+          }
           i = j;
         }
         // bundles: four blocks of one half mask (blocks are sorted by mask first)
