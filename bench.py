@@ -295,8 +295,9 @@ def main():
     ap.add_argument("--no-recon", action="store_true",
                     help="skip the full and refined reconstructions (for profiler passes)")
     ap.add_argument("--serve-modes", default="fifo_fp32,served_bf16r")
-    ap.add_argument("--serve-budget-gb", type=float, default=4.0,
-                    help="device-memory budget of the scheduler's admission (GiB)")
+    ap.add_argument("--serve-budget-gb", type=float, default=6.0,
+                    help="device-memory budget of the scheduler's admission (GiB; small enough "
+                         "that two of the mix's largest requests are not resident together)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -213,15 +213,18 @@ __device__ __forceinline__ void stage_rows(const StagedArgs& a, const T* __restr
 }
 
 // Position fragments of one bundle for the NT tiles of this lane: 16 bytes each from LDS.
-template <typename T, int NT>
+// Tiles t with t % TPR >= NTC (16-position tiles beyond the last scan column, in a patch at
+// the grid's edge) are left out.
+template <typename T, int NT, int TPR = 1, int NTC = TPR>
 __device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int mo,
                                        u32x4 (&x)[NT]) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) x[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + mo);
+  for (int t = 0; t < NT; ++t)
+    if (t % TPR < NTC) x[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + mo);
 }
 
-// MFMAs of one bundle whose position fragments are already in registers.
-template <typename T, int MH, int NT>
+// MFMAs of one bundle whose position fragments are already in registers (tiles as read_x).
+template <typename T, int MH, int NT, int TPR = 1, int NTC = TPR>
 __device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&xraw)[NT],
                                            floatx4 (&acc)[MH][NT]) {
 #pragma unroll
@@ -230,6 +233,7 @@ __device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&
     const u32x4 araw = f.v[h];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
+      if (t % TPR >= NTC) continue;
       if constexpr (sizeof(T) == 4) {
         const floatx4 av = __builtin_bit_cast(floatx4, araw);
         const floatx4 xv = __builtin_bit_cast(floatx4, xraw[t]);
@@ -246,6 +250,29 @@ __device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&
   }
 }
 
+// FP32 bundles [U.z, U.w) of one stage unit for the tiles of the NTC live tile columns: the
+// next bundle's position fragments are read while this bundle's 16 MFMAs run (two register
+// sets), and ring slot (j + 1) mod PD holds the next bundle (or a clamped copy of the last).
+template <int MH, int NT, int TPR, int NTC, int PD>
+__device__ __forceinline__ void fp32_unit_bundles(const float* lds, const int (&lbase)[NT],
+                                                  AFrag<float, MH> (&ring)[PD],
+                                                  floatx4 (&acc)[MH][NT],
+                                                  const void* __restrict__ pack_raw,
+                                                  const StagedArgs& a, int4 U, int g, int n) {
+  u32x4 xa[NT], xb[NT];
+  read_x<float, NT, TPR, NTC>(lds, lbase, ring[0].mo, xa);
+  for (int b0 = U.z; b0 < U.w; b0 += PD) {
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+      read_x<float, NT, TPR, NTC>(lds, lbase, ring[(j + 1) % PD].mo, (j % 2) ? xa : xb);
+      if (b0 + j < U.w) bundle_mma<float, MH, NT, TPR, NTC>(ring[j], (j % 2) ? xb : xa, acc);
+      // refill unconditionally (clamped to the unit's last bundle) so that the number of
+      // loads in flight is fixed and the waits can count them
+      load_a<float, MH>(pack_raw, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
+    }
+  }
+}
+
 // LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 rows) and one patch
 // of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT 16-position
 // tiles.  The tile's bundles are grouped into stage units (chunk, input row offset).  The LDS
@@ -256,8 +283,11 @@ __device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&
 // PD-deep register ring that runs across unit boundaries.  Lane (n = lane % 16,
 // g = lane / 16) holds row n of K-group g of the table and the entries of K-group g for
 // position n.
+// Two waves per SIMD (the LDS holds two workgroups of the 81 x 81 footprint): with that
+// target the compiler keeps the accumulators in VGPRs and the next bundle's reads ahead of the
+// MFMAs.
 template <typename T, int BR, int BC, int MH>
-__global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ pack_raw,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply_staged(const void* __restrict__ pack_raw,
                                                       const T* __restrict__ in,
                                                       float* __restrict__ out, StagedArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -314,21 +344,21 @@ __global__ __launch_bounds__(256) void k_apply_staged(const void* __restrict__ p
         const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
         lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
       }
-      if constexpr (sizeof(T) == 4) {
-        // FP32: the next bundle's position fragments are read while this bundle's 16 MFMAs
-        // run (two register sets; the FP32 kernel has the registers to spare)
-        u32x4 xa[NT], xb[NT];
-        read_x<T, NT>(lds, lbase, ring[0].mo, xa);
-        for (int b0 = U.z; b0 < U.w; b0 += PD) {
-#pragma unroll
-          for (int j = 0; j < PD; ++j) {
-            // slot (j + 1) mod PD holds the next bundle (or a clamped copy of the last one)
-            read_x<T, NT>(lds, lbase, ring[(j + 1) % PD].mo, (j % 2) ? xa : xb);
-            if (b0 + j < U.w) bundle_mma<T, MH, NT>(ring[j], (j % 2) ? xb : xa, acc);
-            // refill unconditionally (clamped to the unit's last bundle) so that the number
-            // of loads in flight is fixed and the waits can count them
-            load_a<T, MH>(pack_raw, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
-          }
+      // FP32: a wave whose rows read only the zero rows around the scan grid at this unit's
+      // row offset skips the unit's MFMAs (it still stages its share of the unit's rows).  The
+      // BF16 loop, compiled with that branch, ran slower than it gains.
+      const int src_row = py0 + wave * RW + U.x;
+      const bool live = sizeof(T) != 4 || (src_row + RW > 0 && src_row < a.ny);
+      if (!live) {
+      } else if constexpr (sizeof(T) == 4) {
+        // a patch at the grid's last columns computes only its tiles that hold scan columns
+        if constexpr (TPR == 2) {
+          if (px0 + 16 >= a.nx)
+            fp32_unit_bundles<MH, NT, TPR, 1, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
+          else
+            fp32_unit_bundles<MH, NT, TPR, TPR, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
+        } else {
+          fp32_unit_bundles<MH, NT, TPR, TPR, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
         }
       } else {
         // BF16: one register set for the position fragments (a second one would cost
