@@ -540,43 +540,36 @@ struct Fp8Args {
   int NCOL, CS;
 };
 
-// Table operand of one FP8 bundle for one lane: 32 bytes per half, and the bundle's record
-// (16 words, the same for the whole wave, so it comes through the scalar path: word 4 g + i
-// of lane group g; word 3 holds the half mask).
+// Table operand of one FP8 bundle for one lane: 32 bytes per half.
 struct F8Frag {
   u32x4 v[2][2];
-  uint32_t w[16];
 };
 
-__device__ __forceinline__ void load_f8(const uint8_t* __restrict__ pack, const Fp8Args& a,
-                                        int b, int lane, F8Frag& f) {
+__device__ __forceinline__ void load_f8(const uint8_t* __restrict__ pack, int b, int lane,
+                                        F8Frag& f) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const u32x4* p = reinterpret_cast<const u32x4*>(pack + (((long long)b * 2 + h) * 64 + lane) * 32);
     f.v[h][0] = p[0];
     f.v[h][1] = p[1];
   }
-  const uint32_t* r = reinterpret_cast<const uint32_t*>(a.rec) + (long long)b * 16;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) f.w[i] = r[i];
 }
 
-// Word i of lane group g's part of a bundle record, selected with masks (no branches):
-// m1 / m2 are all ones where bit 0 / bit 1 of g is set.
-__device__ __forceinline__ uint32_t rec_word(const F8Frag& f, uint32_t m1, uint32_t m2, int i) {
-  const uint32_t lo = (f.w[i] & ~m1) | (f.w[4 + i] & m1);
-  const uint32_t hi = (f.w[8 + i] & ~m1) | (f.w[12 + i] & m1);
-  return (lo & ~m2) | (hi & m2);
+// The four record words of lane group g for bundle b.  Vector loads: a lane needs only its own
+// lane group's words, and a record that came through the scalar path would make every wait on
+// the LDS reads wait for it as well (scalar loads complete out of order, so the shared counter
+// can only be waited to zero).
+__device__ __forceinline__ u32x4 load_rec8(const Fp8Args& a, int b, int g) {
+  return a.rec[(long long)b * kLaneGroups + g];
 }
 
-// LDS offsets of the lane group's four K-groups in an FP8 bundle.
+// LDS offsets of the lane group's four K-groups in an FP8 bundle (record words 0 and 1).
 struct X8Offs {
   int o[4];
 };
 
-__device__ __forceinline__ X8Offs x8_offsets(const F8Frag& f, uint32_t m1, uint32_t m2) {
-  const uint32_t r0 = rec_word(f, m1, m2, 0), r1 = rec_word(f, m1, m2, 1);
-  return X8Offs{{(int)(r0 & 0xffff), (int)(r0 >> 16), (int)(r1 & 0xffff), (int)(r1 >> 16)}};
+__device__ __forceinline__ X8Offs x8_offsets(const u32x4& r) {
+  return X8Offs{{(int)(r.x & 0xffff), (int)(r.x >> 16), (int)(r.y & 0xffff), (int)(r.y >> 16)}};
 }
 
 // Position fragments of one FP8 bundle for the NT tiles of this lane: for each of the lane
@@ -646,13 +639,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int NT = RW * TPR;
   constexpr int PF = 4;
   constexpr int PD = 2;                // table-fragment ring depth (bundles)
+  constexpr int RQ = 4;                // record ring depth (bundles; a multiple of PD)
   constexpr int MH = 2;
   const int4 piece = a.pieces[blockIdx.y];
   const int tile = piece.x;
   const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int n = lane % 16, g = lane / 16;
-  const uint32_t m1 = 0u - (uint32_t)(g & 1), m2 = 0u - (uint32_t)((g >> 1) & 1);
   constexpr int nvec = 4;              // 16-byte vectors per staged column (64-byte chunk)
   const int rowvec = a.NCOL * nvec;
   StagedArgs sa;                       // the staging helpers' view of the arguments
@@ -673,10 +666,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     u32x4 pf[PF];
     int pf_off[PF];
     F8Frag ring[PD];
+    u32x4 rq[RQ];
     {
       const int4 U = a.units[u0];
 #pragma unroll
-      for (int j = 0; j < PD; ++j) load_f8(pack, a, min(U.z + j, U.w - 1), lane, ring[j]);
+      for (int j = 0; j < PD; ++j) load_f8(pack, min(U.z + j, U.w - 1), lane, ring[j]);
+#pragma unroll
+      for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(U.z + j, U.w - 1), g);
       stage_prefetch<uint8_t, RS, PF>(sa, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
       stage_rows<uint8_t, RS, PF>(sa, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
       __syncthreads();
@@ -692,32 +688,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
         lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
       }
-      // the next bundle's position fragments are read while this bundle's MFMAs run (two
-      // register sets; ring slot (j + 1) mod PD holds the next bundle or a clamped copy)
-      // The bundle's record words come through the scalar path, whose loads complete out of
-      // order, so their first use waits for every LDS read in flight too: the current bundle's
-      // scale and mask and the next bundle's offsets are taken before the next bundle's reads
-      // are issued (the scheduling barriers keep that order).
+      // The next bundle's position fragments are read while this bundle's MFMAs run (two
+      // register sets).  Table slot j mod PD holds bundle b0 + j, record slot j bundle b0 + j
+      // (or clamped copies of the unit's last bundle); records are loaded RQ bundles ahead,
+      // since the next bundle's LDS offsets are needed a bundle before its table fragments.
+      // The scheduling barriers keep the next bundle's reads ahead of this bundle's MFMAs.
       u32x4 xa[NT][2], xb[NT][2];
-      read_x8<NT>(lds, lbase, x8_offsets(ring[0], m1, m2), xa);
-      for (int b0 = U.z; b0 < U.w; b0 += PD) {
+      read_x8<NT>(lds, lbase, x8_offsets(rq[0]), xa);
+      for (int b0 = U.z; b0 < U.w; b0 += RQ) {
 #pragma unroll
-        for (int j = 0; j < PD; ++j) {
-          const int sc = (int)rec_word(ring[j], m1, m2, 2);
-          const int hm = b0 + j < U.w ? (int)ring[j].w[3] : 0;
-          const X8Offs on = x8_offsets(ring[(j + 1) % PD], m1, m2);
+        for (int j = 0; j < RQ; ++j) {
+          const int sc = (int)rq[j].z;  // the lane group's block scale bytes
+          // the 16-row halves the bundle reaches: word 3 of lane group 0 (lane 0's record)
+          const int hm = b0 + j < U.w ? __builtin_amdgcn_readfirstlane((int)rq[j].w) : 0;
+          const X8Offs on = x8_offsets(rq[(j + 1) % RQ]);
           __builtin_amdgcn_sched_barrier(0);
           read_x8<NT>(lds, lbase, on, (j % 2) ? xa : xb);
           __builtin_amdgcn_sched_barrier(0);
-          fp8_mma<NT>(ring[j], sc, hm, xs, (j % 2) ? xb : xa, acc);
-          load_f8(pack, a, min(b0 + j + PD, U.w - 1), lane, ring[j]);
+          fp8_mma<NT>(ring[j % PD], sc, hm, xs, (j % 2) ? xb : xa, acc);
+          load_f8(pack, min(b0 + j + PD, U.w - 1), lane, ring[j % PD]);
+          rq[j] = load_rec8(a, min(b0 + j + RQ, U.w - 1), g);
         }
       }
       if (u + 1 < u1) {
         const int4 Un = a.units[u + 1];
         const int2 Rn = a.urows[u + 1];
 #pragma unroll
-        for (int j = 0; j < PD; ++j) load_f8(pack, a, min(Un.z + j, Un.w - 1), lane, ring[j]);
+        for (int j = 0; j < PD; ++j) load_f8(pack, min(Un.z + j, Un.w - 1), lane, ring[j]);
+#pragma unroll
+        for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(Un.z + j, Un.w - 1), g);
         const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
         if (!free_slot) __syncthreads();
         stage_rows<uint8_t, RS, PF>(sa, in, lds, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
