@@ -108,7 +108,6 @@ struct StagedArgs {
   const int4* units;  // (row offset, chunk start, bundle begin, bundle end)
   const int2* urows;  // padded patch rows [lo, hi) each unit loads into the LDS ring
   const int* meta;
-  const int* bmask;   // per bundle: the 16-row halves of the tile its K-groups reach
   int out_len, nx, ny, K, nxp, Lp;
   int ncc;            // patch column chunks
   int NCOL, CS;
@@ -118,14 +117,13 @@ struct StagedArgs {
 template <typename T, int MH>
 struct AFrag {
   u32x4 v[MH];
-  int mo;
-  int hm;  // halves to issue (bit h: half h); uniform over the wave
+  int mo;  // the K-group's meta word: LDS offset (and for MH > 1 the bundle's half mask)
 };
 
 template <typename T, int MH>
 __device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
                                        const int* __restrict__ meta,
-                                       const int* __restrict__ bmask, int b, int g, int n,
+                                       int b, int g, int n,
                                        AFrag<T, MH>& f) {
   const int q = b * kLaneGroups + g;
 #pragma unroll
@@ -134,8 +132,7 @@ __device__ __forceinline__ void load_a(const void* __restrict__ pack_raw,
     constexpr int VEC = 16 / sizeof(T);
     f.v[h] = *reinterpret_cast<const u32x4*>(reinterpret_cast<const T*>(pack_raw) + row * VEC);
   }
-  f.mo = meta[q];
-  f.hm = MH > 1 ? bmask[b] : 1;
+  f.mo = meta[q];  // raw word: for MH > 1 the bundle's half mask sits in its top bits
 }
 
 // Global source and LDS destination of flat stage vector idx of a unit that loads padded
@@ -218,6 +215,7 @@ __device__ __forceinline__ void stage_rows(const StagedArgs& a, const T* __restr
 template <typename T, int NT, int TPR = 1, int NTC = TPR>
 __device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int mo,
                                        u32x4 (&x)[NT]) {
+  if constexpr (sizeof(T) == 2) mo &= (1 << kMetaMaskShift) - 1;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
     if (t % TPR < NTC) x[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + mo);
@@ -227,9 +225,10 @@ __device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int
 template <typename T, int MH, int NT, int TPR = 1, int NTC = TPR>
 __device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&xraw)[NT],
                                            floatx4 (&acc)[MH][NT]) {
+  const int hm = MH > 1 ? __builtin_amdgcn_readfirstlane(f.mo) >> kMetaMaskShift : 1;
 #pragma unroll
   for (int h = 0; h < MH; ++h) {
-    if (MH > 1 && !((f.hm >> h) & 1)) continue;  // the bundle's bands miss this half
+    if (MH > 1 && !((hm >> h) & 1)) continue;  // the bundle's bands miss this half
     const u32x4 araw = f.v[h];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -268,7 +267,7 @@ __device__ __forceinline__ void fp32_unit_bundles(const float* lds, const int (&
       if (b0 + j < U.w) bundle_mma<float, MH, NT, TPR, NTC>(ring[j], (j % 2) ? xb : xa, acc);
       // refill unconditionally (clamped to the unit's last bundle) so that the number of
       // loads in flight is fixed and the waits can count them
-      load_a<float, MH>(pack_raw, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
+      load_a<float, MH>(pack_raw, a.meta, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
     }
   }
 }
@@ -328,7 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int4 U = a.units[u0];
 #pragma unroll
       for (int j = 0; j < PD; ++j)
-        load_a<T, MH>(pack_raw, a.meta, a.bmask, min(U.z + j, U.w - 1), g, n, ring[j]);
+        load_a<T, MH>(pack_raw, a.meta, min(U.z + j, U.w - 1), g, n, ring[j]);
       stage_prefetch<T, RS, PF>(a, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
       stage_rows<T, RS, PF>(a, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
       __syncthreads();
@@ -371,7 +370,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
               read_x<T, NT>(lds, lbase, ring[j].mo, x);
               bundle_mma<T, MH, NT>(ring[j], x, acc);
             }
-            load_a<T, MH>(pack_raw, a.meta, a.bmask, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
+            load_a<T, MH>(pack_raw, a.meta, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
           }
         }
       }
@@ -381,7 +380,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // the next unit's first table fragments; their loads overlap the staging below
 #pragma unroll
         for (int j = 0; j < PD; ++j)
-          load_a<T, MH>(pack_raw, a.meta, a.bmask, min(Un.z + j, Un.w - 1), g, n, ring[j]);
+          load_a<T, MH>(pack_raw, a.meta, min(Un.z + j, Un.w - 1), g, n, ring[j]);
         // one new row right after this unit's rows: its slot is the free one
         const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
         if (!free_slot) __syncthreads();  // every wave is done reading the rows replaced
@@ -841,7 +840,6 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
   a.units = lay.d_units;
   a.urows = lay.d_ucols;
   a.meta = lay.d_meta;
-  a.bmask = lay.d_bmask;
   a.out_len = lay.out_len;
   a.nx = lay.in.nx;
   a.ny = lay.in.ny;

@@ -65,6 +65,10 @@ struct PadGeom {
   long long elems() const { return (long long)nyp * nxp * Lp; }
 };
 
+// Staged layouts of two row halves: bits kMetaMaskShift.. of each K-group's meta word hold
+// its bundle's half mask (the LDS offset stays below 2^kMetaMaskShift).
+constexpr int kMetaMaskShift = 28;
+
 // Band tiles of one operator (forward: rows = time, K = (offset, depth); adjoint: rows =
 // depth, K = (offset, time)) at one K-group width G.  A K-group is G consecutive entries of
 // one table column block; four K-groups form a bundle, which one MFMA step consumes.
@@ -76,7 +80,8 @@ struct PadGeom {
 //    (dy, chunk of CH inner entries).  A workgroup loads the input rows of its position patch
 //    shifted by dy, for the chunk and the unit's dx range, into LDS once, and then sweeps all
 //    (dx, G-run) K-groups of the unit from LDS; meta[q] is then the LDS element offset
-//    (dx + K) * CS + (run start - chunk start).
+//    (dx + K) * CS + (run start - chunk start), for two row halves with the bundle's half
+//    mask in the top bits.
 struct Layout {
   int G = 0;
   int TM = 16;              // output rows per tile (16 or 32: two MFMA row halves)
@@ -85,7 +90,6 @@ struct Layout {
   long long n_bundles = 0;
   int* d_tile_start = nullptr;   // [n_tiles + 1] bundle range of each tile (direct form)
   int* d_meta = nullptr;         // [n_bundles * 4] per K-group offset (see above)
-  int* d_bmask = nullptr;        // staged form: [n_bundles] 16-row halves the bundle reaches
   int4* d_groups = nullptr;      // [n_bundles * 4] (offset index, start, tile, active)
   std::vector<int> h_tile_start;  // bundle (direct) or stage-unit (staged) range of each tile
   long long mac_exec = 0;        // MACs issued per apply

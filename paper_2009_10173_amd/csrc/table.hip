@@ -652,6 +652,9 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
           if (i % kLaneGroups == 0) bmask.push_back(0);
           bmask.back() |= e.mask;
         }
+        if (NH > 1)  // the bundle's half mask rides in the top bits of its K-groups' offsets
+          for (size_t q = first; q < groups.size(); ++q)
+            meta[q] |= bmask[q / kLaneGroups] << kMetaMaskShift;
         const int lo = (prevR < 0 || R >= prevR + BR) ? R : prevR + BR;
         units.push_back(make_int4(R - K, c * CH, (int)(first / kLaneGroups),
                                   (int)(groups.size() / kLaneGroups)));
@@ -675,7 +678,6 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
   AROAM_TRY(alloc_copy(&lay.d_ucols, urows, bytes));
   AROAM_TRY(alloc_copy(&lay.d_meta, meta, bytes));
-  AROAM_TRY(alloc_copy(&lay.d_bmask, bmask, bytes));
   AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
   lay.h_tile_start = tile_units;
   lay.n_patches = (int)(ceil_div(g.ny, BR) * ceil_div(g.nx, BC));
@@ -860,7 +862,6 @@ int build_fp8_layout(const Model& m, bool adjoint, const std::vector<float>& bsc
   AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
   AROAM_TRY(alloc_copy(&lay.d_ucols, urows, bytes));
   AROAM_TRY(alloc_copy(&lay.d_meta, rec, bytes));
-  AROAM_TRY(alloc_copy(&lay.d_bmask, bmask, bytes));
   AROAM_TRY(alloc_copy(&lay.d_groups, groups, bytes));
   lay.h_tile_start = tile_units;
   lay.n_patches = (int)(ceil_div(g.ny, BR) * ceil_div(g.nx, BC));
@@ -1486,7 +1487,6 @@ void destroy_model(Model* m) {
   for (Layout* l : {&m->g4f, &m->g4a, &m->s4f, &m->s4a, &m->s8f, &m->s8a, &m->f8f, &m->f8a}) {
     (void)hipFree(l->d_tile_start);
     (void)hipFree(l->d_meta);
-    (void)hipFree(l->d_bmask);
     (void)hipFree(l->d_groups);
     (void)hipFree(l->d_pieces);
     (void)hipFree(l->d_tile_split);
