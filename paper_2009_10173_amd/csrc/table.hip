@@ -670,9 +670,32 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
   tile_units[lay.n_tiles] = (int)units.size();
   lay.n_units = (long long)units.size();
   lay.n_bundles = (long long)groups.size() / kLaneGroups;
-  long long halves = 0;  // 16-row MFMA halves the kernel issues
-  for (int bm : bmask) halves += __builtin_popcount((unsigned)bm);
-  lay.mac_exec = halves * kLaneGroups * kTile * G * (round_up(g.ny, BR) * round_up(g.nx, BC));
+  // MACs the kernel issues: per bundle, its 16-row halves times the positions of every patch.
+  // The FP32 kernel (esize 4) leaves out two things: a wave's MFMAs for a unit whose row
+  // offset makes its BR / 4 rows read only the zero rows around the grid, and the second
+  // 16-position tile column of a patch that holds at most 16 scan columns.
+  long long mac_exec = 0;
+  {
+    const int RW = BR / 4;
+    const long long cols =
+        esize == 4 && BC == 32 && g.nx % BC > 0 && g.nx % BC <= 16
+            ? (long long)(g.nx / BC) * BC + 16
+            : round_up(g.nx, BC);
+    std::vector<long long> rows_live(W, 0);  // computed rows per row offset dy (index dy + K)
+    for (int d = 0; d < W; ++d)
+      for (int py0 = 0; py0 < g.ny; py0 += BR)
+        for (int w = 0; w < 4; ++w) {
+          const int src = py0 + w * RW + d - K;
+          if (esize != 4 || (src + RW > 0 && src < g.ny)) rows_live[d] += RW;
+        }
+    for (size_t u = 0; u < units.size(); ++u) {
+      long long halves = 0;
+      for (int b = units[u].z; b < units[u].w; ++b) halves += __builtin_popcount((unsigned)bmask[b]);
+      mac_exec += halves * rows_live[units[u].x + K];
+    }
+    mac_exec *= (long long)kLaneGroups * kTile * G * cols;
+  }
+  lay.mac_exec = mac_exec;
   AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
               "grid too large for 32-bit operand offsets (%lld padded elements)", lay.in.elems());
   AROAM_TRY(alloc_copy(&lay.d_units, units, bytes));
