@@ -215,7 +215,7 @@ __device__ __forceinline__ void stage_rows(const StagedArgs& a, const T* __restr
 template <typename T, int NT, int TPR = 1, int NTC = TPR>
 __device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int mo,
                                        u32x4 (&x)[NT]) {
-  if constexpr (sizeof(T) == 2) mo &= (1 << kMetaMaskShift) - 1;
+  mo &= (1 << kMetaMaskShift) - 1;  // the top bits hold the bundle's mask
 #pragma unroll
   for (int t = 0; t < NT; ++t)
     if (t % TPR < NTC) x[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + mo);
@@ -225,23 +225,30 @@ __device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int
 template <typename T, int MH, int NT, int TPR = 1, int NTC = TPR>
 __device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&xraw)[NT],
                                            floatx4 (&acc)[MH][NT]) {
-  const int hm = MH > 1 ? __builtin_amdgcn_readfirstlane(f.mo) >> kMetaMaskShift : 1;
+  // the bundle's mask: for FP32 the entries of its runs (one MFMA each) that a K-group's band
+  // reaches, for BF16 the 16-row halves; uniform over the wave
+  const unsigned bm = (unsigned)__builtin_amdgcn_readfirstlane(f.mo) >> kMetaMaskShift;
+  if constexpr (sizeof(T) == 4) {
+    static_assert(MH == 1, "FP32 tiles have one 16-row half");
+    const floatx4 av = __builtin_bit_cast(floatx4, f.v[0]);
 #pragma unroll
-  for (int h = 0; h < MH; ++h) {
-    if (MH > 1 && !((hm >> h) & 1)) continue;  // the bundle's bands miss this half
-    const u32x4 araw = f.v[h];
+    for (int j = 0; j < 4; ++j) {
+      if (!((bm >> j) & 1)) continue;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (t % TPR >= NTC) continue;
-      if constexpr (sizeof(T) == 4) {
-        const floatx4 av = __builtin_bit_cast(floatx4, araw);
+      for (int t = 0; t < NT; ++t) {
+        if (t % TPR >= NTC) continue;
         const floatx4 xv = __builtin_bit_cast(floatx4, xraw[t]);
-        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[h][t], 0, 0, 0);
-        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[h][t], 0, 0, 0);
-        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[h][t], 0, 0, 0);
-        acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[h][t], 0, 0, 0);
-      } else {
-        const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+        acc[0][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], xv[j], acc[0][t], 0, 0, 0);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < MH; ++h) {
+      if (MH > 1 && !((bm >> h) & 1)) continue;  // the bundle's bands miss this half
+      const bf16x8 av = __builtin_bit_cast(bf16x8, f.v[h]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t % TPR >= NTC) continue;
         const bf16x8 xv = __builtin_bit_cast(bf16x8, xraw[t]);
         acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xv, acc[h][t], 0, 0, 0);
       }

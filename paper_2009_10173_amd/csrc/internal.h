@@ -65,8 +65,9 @@ struct PadGeom {
   long long elems() const { return (long long)nyp * nxp * Lp; }
 };
 
-// Staged layouts of two row halves: bits kMetaMaskShift.. of each K-group's meta word hold
-// its bundle's half mask (the LDS offset stays below 2^kMetaMaskShift).
+// Staged layouts: bits kMetaMaskShift.. of each K-group's meta word hold its bundle's mask (the
+// LDS offset stays below 2^kMetaMaskShift): with two row halves the halves its K-groups reach,
+// with one (FP32, runs of 4) the entries of the runs, one MFMA each, that they reach.
 constexpr int kMetaMaskShift = 28;
 
 // Band tiles of one operator (forward: rows = time, K = (offset, depth); adjoint: rows =
@@ -80,8 +81,7 @@ constexpr int kMetaMaskShift = 28;
 //    (dy, chunk of CH inner entries).  A workgroup loads the input rows of its position patch
 //    shifted by dy, for the chunk and the unit's dx range, into LDS once, and then sweeps all
 //    (dx, G-run) K-groups of the unit from LDS; meta[q] is then the LDS element offset
-//    (dx + K) * CS + (run start - chunk start), for two row halves with the bundle's half
-//    mask in the top bits.
+//    (dx + K) * CS + (run start - chunk start), with the bundle's mask in the top bits.
 struct Layout {
   int G = 0;
   int TM = 16;              // output rows per tile (16 or 32: two MFMA row halves)

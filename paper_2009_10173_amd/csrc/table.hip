@@ -333,7 +333,7 @@ bool tile_hits(const Model& m, bool adjoint, int G, int TM, int t, int oi, std::
       if (lo < 0) continue;
       const int hi = m.h_hi[(size_t)oi * nz + k];
       if (lo <= r1 && hi >= r0) {
-        hit[k / G] = 1;
+        hit[k / G] = (char)(hit[k / G] | (1 << (k % G)));
         any = true;
       }
     }
@@ -342,7 +342,7 @@ bool tile_hits(const Model& m, bool adjoint, int G, int TM, int t, int oi, std::
       const int lo = m.h_lo[(size_t)oi * nz + k];
       if (lo < 0) continue;
       const int hi = m.h_hi[(size_t)oi * nz + k];
-      for (int q = lo / G; q <= hi / G; ++q) hit[q] = 1;
+      for (int n = lo; n <= hi; ++n) hit[n / G] = (char)(hit[n / G] | (1 << (n % G)));
       any = true;
     }
   }
@@ -528,11 +528,14 @@ std::vector<UnitEntry> pair_unit(const std::vector<UnitEntry>& in, int maxcol, i
 
 // Order a stage unit's K-groups into bundles.  With two 16-row halves per tile, K-groups
 // are first grouped by the halves their bands reach, so that most bundles reach only one
-// half and the kernel skips the other half's MFMAs; each group is paired for the LDS as above.
+// half and the kernel skips the other half's MFMAs; with one half (FP32, runs of 4), by the
+// entries of their run that the band reaches in the tile, so that the kernel skips the
+// MFMAs of entries no K-group of the bundle reaches.  Each group is paired for the LDS as
+// above.
 std::vector<UnitEntry> order_unit(const std::vector<UnitEntry>& in, int maxcol, int t, int NH) {
-  if (NH == 1) return pair_unit(in, maxcol, t);
   std::vector<UnitEntry> out;
-  for (int mask = 1; mask < (1 << NH); ++mask) {
+  const int nmask = NH > 1 ? 1 << NH : 16;  // half masks, or masks of a run's four entries
+  for (int mask = 1; mask < nmask; ++mask) {
     std::vector<UnitEntry> cls;
     for (const UnitEntry& e : in)
       if (e.mask == mask) cls.push_back(e);
@@ -627,7 +630,9 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
         for (int q = 0; q < nq; ++q) {
           if (!hits[b][q]) continue;
           const int c = q / qpc;
-          int mask = 1;
+          // two row halves: the halves the K-group's band reaches; one half (G = 4): the
+          // entries of the run the band reaches in this tile (one MFMA each)
+          int mask = (unsigned char)hits[b][q] & 15;
           if (NH > 1) {
             mask = 0;
             for (int h = 0; h < NH; ++h) mask |= hhits[(size_t)b * NH + h][q] ? 1 << h : 0;
@@ -652,16 +657,16 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
           if (i % kLaneGroups == 0) bmask.push_back(0);
           bmask.back() |= e.mask;
         }
-        if (NH > 1)  // the bundle's half mask rides in the top bits of its K-groups' offsets
-          for (size_t q = first; q < groups.size(); ++q)
-            meta[q] |= bmask[q / kLaneGroups] << kMetaMaskShift;
+        // the bundle's mask rides in the top bits of its K-groups' offsets
+        for (size_t q = first; q < groups.size(); ++q)
+          meta[q] = (int)((unsigned)meta[q] | ((unsigned)bmask[q / kLaneGroups] << kMetaMaskShift));
         const int lo = (prevR < 0 || R >= prevR + BR) ? R : prevR + BR;
         units.push_back(make_int4(R - K, c * CH, (int)(first / kLaneGroups),
                                   (int)(groups.size() / kLaneGroups)));
         urows.push_back(make_int2(lo, R + BR));
-        double w = 0;
+        double w = 0;  // MFMA halves (one-half tiles: quarters of a bundle's four MFMAs)
         for (size_t b = first / kLaneGroups; b < groups.size() / kLaneGroups; ++b)
-          w += __builtin_popcount((unsigned)bmask[b]);
+          w += __builtin_popcount((unsigned)bmask[b]) * (NH > 1 ? 1.0 : 0.25);
         unit_work.push_back(w);
         prevR = R;
       }
@@ -688,12 +693,15 @@ int build_staged_layout(const Model& m, bool adjoint, int G, int TM, int CH, int
           const int src = py0 + w * RW + d - K;
           if (esize != 4 || (src + RW > 0 && src < g.ny)) rows_live[d] += RW;
         }
+    // per position, a bundle issues 16 rows x 4 K-groups x G entries per reached half, or,
+    // with one half (G = 4), 16 rows x 4 K-groups for each of its four MFMAs it issues
+    const long long per_bit = (long long)kLaneGroups * kTile * (NH > 1 ? G : 1);
     for (size_t u = 0; u < units.size(); ++u) {
-      long long halves = 0;
-      for (int b = units[u].z; b < units[u].w; ++b) halves += __builtin_popcount((unsigned)bmask[b]);
-      mac_exec += halves * rows_live[units[u].x + K];
+      long long bits = 0;
+      for (int b = units[u].z; b < units[u].w; ++b) bits += __builtin_popcount((unsigned)bmask[b]);
+      mac_exec += bits * rows_live[units[u].x + K];
     }
-    mac_exec *= (long long)kLaneGroups * kTile * G * cols;
+    mac_exec *= per_bit * cols;
   }
   lay.mac_exec = mac_exec;
   AROAM_CHECK(lay.in.elems() < (1ll << 31), AROAM_EINVAL,
