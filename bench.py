@@ -411,9 +411,11 @@ def main():
     if args.serve_requests > 0:
         log(f"serving leg: {args.serve_requests} mixed requests")
         from paper_2009_10173_amd import serve as S
+        # the large-request policy stays off here, so that the leg shows the admission budget
+        # binding (profiles/serving_mixed40.md measures the policy)
         res = S.main(["--requests", str(args.serve_requests), "--calibrate", "predict",
-                      "--modes", args.serve_modes, "--budget-gb", str(args.serve_budget_gb)],
-                     quiet=True)
+                      "--modes", args.serve_modes, "--budget-gb", str(args.serve_budget_gb),
+                      "--large-s", "0"], quiet=True)
         result["serving"] = res
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

@@ -338,6 +338,21 @@ int aroam_solve_footprint(const aroam_model* model, int kind, const aroam_solve_
 typedef struct aroam_server aroam_server;
 int aroam_server_create(size_t hbm_budget_bytes, int max_slots, int tick_iters,
                         aroam_server** out);
+/* Large-request policy (for the latency tail of a mix of small and large requests): a
+ * request whose whole solve takes at least `large_macs` multiply-accumulates (A + A^T pairs
+ * of the solve times the model's algorithmic MACs per apply: LSQR (iters + 1) per sweep,
+ * FISTA power_iters + iters + 1) is large, and at most one large request is resident.  A
+ * large request that would be the second waits at its place in the queue.  With
+ * large_alone = 0 the requests behind it that are not large are admitted past it; with
+ * large_alone = 1 no request is admitted while a large one is resident, so that a large
+ * request shares the device only with the requests admitted before it.  large_macs = 0 (the
+ * default) turns the policy off.  Set before the first submission.  Errors: AROAM_EINVAL
+ * (NULL server, negative threshold, requests already submitted). */
+int aroam_server_set_large(aroam_server* server, double large_macs, int large_alone);
+/* Admission counters: the polls after which a request waited although a slot was free,
+ * because it did not fit the budget (*by_budget) or because of the large-request policy
+ * (*by_large).  Either pointer may be NULL.  Errors: AROAM_EINVAL (NULL server). */
+int aroam_server_held(const aroam_server* server, long long* by_budget, long long* by_large);
 /* Queue a request; *id (may be NULL) receives its identifier (1, 2, ...). */
 int aroam_server_submit(aroam_server* server, const aroam_model* model, int kind,
                         const aroam_solve_opts* opts, const void* s, void* x, long long* id);

@@ -10,5 +10,5 @@ from .binding import (  # noqa: F401
     aroam_last_error, aroam_model_destroy, aroam_model_export_quantized, aroam_model_export_table,
     aroam_model_query,
     aroam_server_collect, aroam_server_create, aroam_server_destroy, aroam_server_poll,
-    aroam_server_submit, aroam_solve_footprint, aroam_solve_l1, aroam_solve_lsqr, library_path,
+    aroam_server_held, aroam_server_set_large, aroam_server_submit, aroam_solve_footprint, aroam_solve_l1, aroam_solve_lsqr, library_path,
     load_library)

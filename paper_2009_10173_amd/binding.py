@@ -93,6 +93,9 @@ _SYMBOLS = {
     "aroam_solve_footprint": ([C.c_void_p, C.c_int, C.POINTER(SolveOpts),
                                C.POINTER(C.c_size_t)], C.c_int),
     "aroam_server_create": ([C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "aroam_server_set_large": ([C.c_void_p, C.c_double, C.c_int], C.c_int),
+    "aroam_server_held": ([C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)],
+                          C.c_int),
     "aroam_server_submit": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(SolveOpts), C.c_void_p,
                              C.c_void_p, C.POINTER(C.c_longlong)], C.c_int),
     "aroam_server_poll": ([C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
@@ -328,6 +331,17 @@ def aroam_server_create(hbm_budget_bytes, max_slots=8, tick_iters=2):
     _check(load_library().aroam_server_create(int(hbm_budget_bytes), int(max_slots),
                                               int(tick_iters), C.byref(h)))
     return h
+
+
+def aroam_server_set_large(server, large_macs, large_alone=False):
+    _check(load_library().aroam_server_set_large(server, float(large_macs), int(bool(large_alone))))
+
+
+def aroam_server_held(server):
+    """(polls held by the budget, polls held by the large-request policy)."""
+    b, l = C.c_longlong(), C.c_longlong()
+    _check(load_library().aroam_server_held(server, C.byref(b), C.byref(l)))
+    return b.value, l.value
 
 
 def aroam_server_submit(server, model_h, kind, s, x, **opts):

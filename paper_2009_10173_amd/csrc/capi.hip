@@ -326,6 +326,24 @@ int aroam_server_create(size_t hbm_budget_bytes, int max_slots, int tick_iters,
   return AROAM_OK;
 }
 
+int aroam_server_set_large(aroam_server* server, double large_macs, int large_alone) {
+  aroam::clear_error();
+  if (!server) {
+    aroam::set_error("NULL server");
+    return AROAM_EINVAL;
+  }
+  return aroam::server_set_large(*server->s, large_macs, large_alone);
+}
+
+int aroam_server_held(const aroam_server* server, long long* by_budget, long long* by_large) {
+  aroam::clear_error();
+  if (!server) {
+    aroam::set_error("NULL server");
+    return AROAM_EINVAL;
+  }
+  return aroam::server_held(*server->s, by_budget, by_large);
+}
+
 int aroam_server_submit(aroam_server* server, const aroam_model* model, int kind,
                         const aroam_solve_opts* opts, const void* s, void* x, long long* id) {
   aroam::clear_error();

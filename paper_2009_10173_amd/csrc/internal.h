@@ -217,6 +217,7 @@ class Solver {
 int solver_create(const Model& m, int kind, const aroam_solve_opts& o, const void* s, void* x,
                   hipStream_t st, Solver** out);
 size_t solver_footprint(const Model& m, int kind, const aroam_solve_opts& o);
+double solver_work(const Model& m, int kind, const aroam_solve_opts& o);
 int solve_lsqr(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
                aroam_solve_info* info, hipStream_t st);
 int solve_l1(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
@@ -225,6 +226,8 @@ int solve_l1(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
 // serve.hip
 struct Server;
 int server_create(size_t budget, int max_slots, int tick, Server** out);
+int server_set_large(Server& sv, double large_work, int large_alone);
+int server_held(const Server& sv, long long* by_budget, long long* by_large);
 int server_submit(Server& sv, const Model& m, int kind, const aroam_solve_opts& o, const void* s,
                   void* x, long long* id);
 int server_poll(Server& sv, int* n_resident, int* n_queued);

@@ -4,7 +4,11 @@
 // retires finished requests (freeing their slot and memory), admits queued requests in
 // arrival order while a slot is free and their solver state fits the device-memory budget,
 // and gives every resident request one more tick of iterations on its own stream, so the
-// work of all resident requests is in flight on the device at once.  At most two ticks per
+// work of all resident requests is in flight on the device at once.  With a large-request
+// threshold set, at most one request whose work reaches it is resident: a large request that
+// would be the second waits at its place in the queue, and the requests behind it that are
+// not large may be admitted past it, or, with `large_alone`, nothing is admitted while a large
+// request is resident (it then shares the device only with requests admitted before it).  At most two ticks per
 // request are queued ahead; a request's kernels and their order are the same whether it runs
 // alone or among others, so its result is too.
 #include <hip/hip_runtime.h>
@@ -28,6 +32,8 @@ struct Req {
   const void* s = nullptr;
   void* x = nullptr;
   size_t foot = 0;
+  double work = 0;  // multiply-accumulates of the whole solve (the policy's size measure)
+  bool large = false;
   Solver* sv = nullptr;
   int slot = -1;
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -40,6 +46,12 @@ struct Req {
 struct Server {
   size_t budget = 0, used = 0;
   int max_slots = 0, tick = 1;
+  double large_work = 0;  // 0: no large-request policy
+  bool large_alone = false;
+  int large_resident = 0;
+  // polls after which a request waited although a slot was free, because of the budget or of
+  // the large-request policy
+  long long held_budget = 0, held_large = 0;
   long long next_id = 1;
   std::vector<hipStream_t> streams;
   std::vector<char> busy;
@@ -58,6 +70,7 @@ int retire(Server& sv, Req* r) {
     if (e) (void)hipEventDestroy(e);
   sv.busy[r->slot] = 0;
   sv.used -= r->foot;
+  if (r->large) --sv.large_resident;
   sv.done.push_back(r);
   return AROAM_OK;
 }
@@ -97,6 +110,21 @@ int server_create(size_t budget, int max_slots, int tick, Server** out) {
   return AROAM_OK;
 }
 
+int server_set_large(Server& sv, double large_work, int large_alone) {
+  AROAM_CHECK(large_work >= 0, AROAM_EINVAL, "negative large-request threshold");
+  AROAM_CHECK(sv.queue.empty() && sv.resident.empty(), AROAM_EINVAL,
+              "the large-request threshold is set before the first submission");
+  sv.large_work = large_work;
+  sv.large_alone = large_alone != 0;
+  return AROAM_OK;
+}
+
+int server_held(const Server& sv, long long* by_budget, long long* by_large) {
+  if (by_budget) *by_budget = sv.held_budget;
+  if (by_large) *by_large = sv.held_large;
+  return AROAM_OK;
+}
+
 int server_submit(Server& sv, const Model& m, int kind, const aroam_solve_opts& o, const void* s,
                   void* x, long long* id) {
   AROAM_CHECK(kind == 0 || kind == 1, AROAM_EINVAL, "bad solver kind");
@@ -110,6 +138,8 @@ int server_submit(Server& sv, const Model& m, int kind, const aroam_solve_opts& 
   r->s = s;
   r->x = x;
   r->foot = solver_footprint(m, kind, o);
+  r->work = solver_work(m, kind, o);
+  r->large = sv.large_work > 0 && r->work >= sv.large_work;
   sv.queue.push_back(r);
   if (id) *id = r->id;
   return AROAM_OK;
@@ -126,13 +156,24 @@ int server_poll(Server& sv, int* n_resident, int* n_queued) {
       ++i;
     }
   }
-  // 2. admit in arrival order while a slot is free and the solver state fits the budget
-  while (!sv.queue.empty()) {
-    Req* r = sv.queue.front();
+  // 2. admit in arrival order while a slot is free and the solver state fits the budget; a
+  //    large request that would be the second resident one keeps its place and is passed
+  bool by_budget = false, by_large = false;
+  for (auto it = sv.queue.begin(); it != sv.queue.end();) {
+    Req* r = *it;
     if (r->foot > sv.budget) {  // can never fit: reject
       r->info.status = AROAM_ENOMEM;
       sv.done.push_back(r);
-      sv.queue.pop_front();
+      it = sv.queue.erase(it);
+      continue;
+    }
+    if (sv.large_alone && sv.large_resident > 0) {
+      by_large = true;
+      break;
+    }
+    if (r->large && sv.large_resident > 0) {
+      by_large = true;
+      ++it;
       continue;
     }
     int slot = -1;
@@ -141,8 +182,12 @@ int server_poll(Server& sv, int* n_resident, int* n_queued) {
         slot = k;
         break;
       }
-    if (slot < 0 || sv.used + r->foot > sv.budget) break;
-    sv.queue.pop_front();
+    if (slot < 0) break;
+    if (sv.used + r->foot > sv.budget) {
+      by_budget = true;
+      break;
+    }
+    it = sv.queue.erase(it);
     r->slot = slot;
     int rc = solver_create(*r->m, r->kind, r->o, r->s, r->x, sv.streams[slot], &r->sv);
     if (rc == AROAM_OK) {
@@ -158,7 +203,12 @@ int server_poll(Server& sv, int* n_resident, int* n_queued) {
     }
     sv.busy[slot] = 1;
     sv.used += r->foot;
+    if (r->large) ++sv.large_resident;
     sv.resident.push_back(r);
+  }
+  if (!sv.queue.empty() && (int)sv.resident.size() < sv.max_slots) {
+    if (by_budget) ++sv.held_budget;
+    if (by_large) ++sv.held_large;
   }
   // 3. one more tick for every resident request with fewer than two ticks in flight
   for (Req* r : sv.resident) {

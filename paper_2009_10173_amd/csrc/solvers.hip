@@ -819,6 +819,15 @@ size_t solver_footprint(const Model& m, int kind, const aroam_solve_opts& o) {
   return SolverT<float>::footprint(m, kind, o);
 }
 
+// Multiply-accumulates of a whole solve, for the request scheduler's size policy: A + A^T
+// pairs (LSQR: one per iteration and one for the start, per sweep; FISTA: one per power and
+// per FISTA iteration, one for the start) times the model's algorithmic MACs per apply.
+double solver_work(const Model& m, int kind, const aroam_solve_opts& o) {
+  const double pairs = kind == 0 ? (o.iters + 1.0) * (1.0 + o.refine_sweeps)
+                                 : (double)o.power_iters + o.iters + 1.0;
+  return 2.0 * pairs * (double)m.mac_alg;
+}
+
 int solve_lsqr(const Model& m, const aroam_solve_opts& o, const void* s, void* x,
                aroam_solve_info* info, hipStream_t st) {
   return run_blocking(m, 0, o, s, x, info, st);

@@ -48,6 +48,33 @@ def solver_opts(req, mode):
                    anchor_period=5, anchor_warmup=-1)
 
 
+def work_macs(r, mode):
+    """The scheduler's size measure of a prepared request: MACs of the whole solve (A + A^T
+    pairs as the library counts them, times the model's algorithmic MACs per apply)."""
+    kind, o = solver_opts(r["req"], mode)
+    pairs = ((o["iters"] + 1.0) * (1 + o["refine_sweeps"]) if kind == 0
+             else o["power_iters"] + o["iters"] + 1.0)
+    return 2.0 * pairs * r["model"].info()["mac_alg"]
+
+
+def fp32_mac_rate(reqs, reps=3):
+    """FP32 multiply-accumulates per second of one forward + adjoint pair, on the largest model
+    of the trace (HIP events)."""
+    import torch
+    r = max(reqs, key=lambda r: r["model"].info()["mac_alg"])
+    m = r["model"]
+    x = torch.zeros(m.image_shape, device=r["s"].device)
+    m.adjoint(m.forward(x, "fp32"), "fp32", out=x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        m.adjoint(m.forward(x, "fp32"), "fp32", out=x)
+    e1.record()
+    e1.synchronize()
+    return 2.0 * m.info()["mac_alg"] * reps / (e0.elapsed_time(e1) * 1e-3)
+
+
 def pairs_of(req, mode):
     """A+A^T pairs (any precision) one request performs."""
     kind, o = solver_opts(req, mode)
@@ -106,18 +133,22 @@ def _progress(verbose, msg):
         print(f"[serve] {msg}", file=sys.stderr, flush=True)
 
 
-def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbose=False):
-    """Replay the arrival times through the scheduler; returns per-request records.  Also
-    counts the polls after which a request waited although a slot was free: the device-memory
-    budget held it back (admission by HBM footprint binding)."""
+def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbose=False,
+               large_macs=0.0, large_alone=False):
+    """Replay the arrival times through the scheduler; returns per-request records and the
+    scheduler's counts of polls after which a request waited although a slot was free,
+    because of the device-memory budget or of the one-large-request policy (`large_macs` >
+    0)."""
     import torch
     torch.cuda.synchronize()
     srv = B.aroam_server_create(budget_bytes, slots, tick)
     try:
+        if large_macs > 0:
+            B.aroam_server_set_large(srv, large_macs, large_alone)
         order = sorted(range(len(reqs)), key=lambda i: reqs[i]["req"]["arrival_s"])
         by_id, rec = {}, {}
         t0 = time.perf_counter()
-        nxt, max_res, budget_waits = 0, 0, 0
+        nxt, max_res = 0, 0
         while len(rec) < len(reqs):
             now = time.perf_counter() - t0
             while nxt < len(order) and reqs[order[nxt]]["req"]["arrival_s"] * time_scale <= now:
@@ -128,8 +159,6 @@ def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbos
                 nxt += 1
             nres, nq = B.aroam_server_poll(srv)
             max_res = max(max_res, nres)
-            if nq > 0 and nres < slots:
-                budget_waits += 1
             done = B.aroam_server_collect(srv)
             tnow = time.perf_counter() - t0
             for rid, info in done:
@@ -144,11 +173,17 @@ def run_served(reqs, mode, budget_bytes, slots=8, tick=2, time_scale=1.0, verbos
             elif not done:
                 time.sleep(0.0002)
         wall = max(r["done_at"] for r in rec.values())
+        held_budget, held_large = B.aroam_server_held(srv)
     finally:
         B.aroam_server_destroy(srv)
+    n_large = sum(1 for r in reqs if large_macs > 0 and work_macs(r, mode) >= large_macs)
     return _summary(reqs, rec, mode, wall, extra=dict(max_resident=max_res, slots=slots,
                                                       tick=tick, budget_bytes=budget_bytes,
-                                                      polls_held_by_budget=budget_waits))
+                                                      polls_held_by_budget=held_budget,
+                                                      polls_held_by_large_policy=held_large,
+                                                      large_macs=large_macs,
+                                                      large_alone=large_alone,
+                                                      large_requests=n_large))
 
 
 def run_fifo(reqs, mode, time_scale=1.0, verbose=False):
@@ -231,6 +266,12 @@ def main(argv=None, quiet=False):
                          "time, or predict it from each model's measured pair time")
     ap.add_argument("--modes", default="fifo_fp32,served_fp32,served_bf16r",
                     help="legs to run (comma-separated)")
+    ap.add_argument("--large-s", type=float, default=1.0,
+                    help="one-large-request policy of the scheduler: requests whose solve "
+                         "takes at least this many seconds of FP32 applies (at the measured "
+                         "FP32 MAC rate) are large, and at most one is resident; 0 = off")
+    ap.add_argument("--large-alone", action="store_true",
+                    help="with --large-s: admit nothing while a large request is resident")
     ap.add_argument("--verbose", action="store_true", help="print every completion")
     args = ap.parse_args(argv)
     W = _workloads()
@@ -265,12 +306,18 @@ def main(argv=None, quiet=False):
                sides=list(sides), nz=list(nzs), load=args.load)
     modes = args.modes.split(",")
     budget = int(args.budget_gb * 2 ** 30)
+    large_macs = 0.0
+    if args.large_s > 0:
+        large_macs = args.large_s * fp32_mac_rate(reqs)
+        res["large_s"] = args.large_s
+        res["large_macs"] = large_macs
     for leg in modes:
         if leg == "fifo_fp32":
             res[leg] = run_fifo(reqs, "fp32", verbose=v)
         elif leg in ("served_fp32", "served_bf16r"):
             res[leg] = run_served(reqs, leg.split("_")[1], budget, args.slots, args.tick,
-                                  verbose=v)
+                                  verbose=v, large_macs=large_macs,
+                                  large_alone=args.large_alone)
         else:
             raise ValueError(f"unknown serving leg {leg}")
         print(f"[serve] {leg} done: p50 {res[leg]['p50_s']:.2f} s, p99 {res[leg]['p99_s']:.2f} s",

@@ -100,6 +100,9 @@ def test_host_side_argument_errors_without_gpu():
     assert "NULL" in P.aroam_last_error()
     assert lib.aroam_forward(None, 1, None, None, None) == -1
     assert lib.aroam_solve_lsqr(None, None, None, None, None, None) == -1
+    assert lib.aroam_server_set_large(None, 1.0, 0) == -1
+    assert lib.aroam_server_held(None, None, None) == -1
+    assert "NULL" in P.aroam_last_error()
     lib.aroam_model_destroy(None)
 
 

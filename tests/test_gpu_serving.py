@@ -33,7 +33,7 @@ def served_setup():
     cache.close()
 
 
-def _run_all(reqs, mode, slots, budget, stagger=False):
+def _run_all(reqs, mode, slots, budget, stagger=False, held=None):
     outs = []
     srv = P.aroam_server_create(budget, slots, 2)
     try:
@@ -52,6 +52,8 @@ def _run_all(reqs, mode, slots, budget, stagger=False):
             for rid, info in P.aroam_server_collect(srv):
                 status[ids[rid]] = info["status"]
                 done += 1
+        if held is not None:
+            held.extend(P.aroam_server_held(srv))
     finally:
         P.aroam_server_destroy(srv)
     torch.cuda.synchronize()
@@ -92,9 +94,12 @@ def test_admission_respects_budget(served_setup):
         feet.append(P.aroam_solve_footprint(r["model"].handle, kind, **o))
     budget = int(max(feet) * 1.5)         # room for one large request at a time
     cap = int(budget // min(feet))
-    _, max_res, st = _run_all(reqs, "bf16r", 8, budget)
+    held = []
+    _, max_res, st = _run_all(reqs, "bf16r", 8, budget, held=held)
     assert all(v == 0 for v in st.values())
     assert 1 <= max_res <= cap
+    print(f"[budget] polls held by the budget {held[0]}, by the large policy {held[1]}")
+    assert held[0] >= 1 and held[1] == 0   # the budget bound while slots were free
 
 
 def test_oversized_request_is_rejected(served_setup):
@@ -130,3 +135,80 @@ def test_served_refined_lsqr_matches_oracle():
     assert abs(done[0][1]["lam"] - lam) <= 1e-5 * lam
     assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-4
     m.close()
+
+
+def test_one_large_request_resident(served_setup):
+    """With the large-request threshold between the LSQR and the FISTA requests' work, the
+    FISTA requests are large: at most one is resident, the second waits at its place while
+    the LSQR requests behind it are admitted, the large ones finish in submission order, and
+    every result equals the request's result without the policy."""
+    _, reqs = served_setup
+    fista = [r for r in reqs if r["req"]["kind"] == "fista"][:2]
+    lsqr = [r for r in reqs if r["req"]["kind"] == "lsqr"][:3]
+    order = [fista[0], fista[1]] + lsqr
+    work = [S.work_macs(r, "fp32") for r in order]
+    large = max(work[2:]) * 1.01
+    assert min(work[:2]) >= large            # the FISTA requests are the large ones
+    ref, _, st = _run_all(order, "fp32", 8, 64 << 30)
+    assert all(v == 0 for v in st.values())
+    srv = P.aroam_server_create(64 << 30, 8, 2)
+    try:
+        P.aroam_server_set_large(srv, large)
+        outs, ids = [], {}
+        for i, r in enumerate(order):
+            kind, o = S.solver_opts(r["req"], "fp32")
+            x = torch.zeros_like(r["x"])
+            outs.append(x)
+            ids[P.aroam_server_submit(srv, r["model"].handle, kind, r["s"], x, **o)] = i
+        with pytest.raises(P.AroamError):      # only before the first submission
+            P.aroam_server_set_large(srv, large)
+        nres, nq = P.aroam_server_poll(srv)
+        print(f"[large policy] after the first poll: {nres} resident, {nq} queued", flush=True)
+        assert (nres, nq) == (len(order) - 1, 1)   # the second FISTA request waits
+        assert P.aroam_server_held(srv) == (0, 1)
+        finished = []
+        while len(finished) < len(order):
+            P.aroam_server_poll(srv)
+            for rid, info in P.aroam_server_collect(srv):
+                assert info["status"] == 0
+                finished.append(ids[rid])
+    finally:
+        P.aroam_server_destroy(srv)
+    torch.cuda.synchronize()
+    assert finished.index(0) < finished.index(1)
+    for a, b in zip(ref, outs):
+        assert torch.equal(a, b)
+
+
+def test_large_request_alone(served_setup):
+    """With large_alone, nothing is admitted while a large request is resident: a large
+    request at the head of the queue is admitted alone, the rest waits, and results are those
+    of the requests without the policy."""
+    _, reqs = served_setup
+    fista = [r for r in reqs if r["req"]["kind"] == "fista"][:1]
+    lsqr = [r for r in reqs if r["req"]["kind"] == "lsqr"][:2]
+    order = fista + lsqr
+    large = max(S.work_macs(r, "fp32") for r in lsqr) * 1.01
+    ref, _, _ = _run_all(order, "fp32", 8, 64 << 30)
+    srv = P.aroam_server_create(64 << 30, 8, 2)
+    try:
+        P.aroam_server_set_large(srv, large, True)
+        outs, ids = [], {}
+        for i, r in enumerate(order):
+            kind, o = S.solver_opts(r["req"], "fp32")
+            x = torch.zeros_like(r["x"])
+            outs.append(x)
+            ids[P.aroam_server_submit(srv, r["model"].handle, kind, r["s"], x, **o)] = i
+        assert P.aroam_server_poll(srv) == (1, 2)
+        finished = []
+        while len(finished) < len(order):
+            P.aroam_server_poll(srv)
+            for rid, info in P.aroam_server_collect(srv):
+                assert info["status"] == 0
+                finished.append(ids[rid])
+    finally:
+        P.aroam_server_destroy(srv)
+    torch.cuda.synchronize()
+    assert finished[0] == 0
+    for a, b in zip(ref, outs):
+        assert torch.equal(a, b)
