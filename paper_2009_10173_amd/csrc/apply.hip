@@ -561,12 +561,19 @@ __device__ __forceinline__ void load_f8(const uint8_t* __restrict__ pack, int b,
   }
 }
 
-// The four record words of lane group g for bundle b.  Vector loads: a lane needs only its own
-// lane group's words, and a record that came through the scalar path would make every wait on
-// the LDS reads wait for it as well (scalar loads complete out of order, so the shared counter
-// can only be waited to zero).
-__device__ __forceinline__ u32x4 load_rec8(const Fp8Args& a, int b, int g) {
-  return a.rec[(long long)b * kLaneGroups + g];
+// One word of lane group g's record for bundle b: lane 4q + j of each quad loads word j, and
+// rec8_word broadcasts word J within the quad (a lane needs only its own lane group's words).
+// Vector loads, since a record that came through the scalar path would make every wait on the
+// LDS reads wait for it as well (scalar loads complete out of order, so the shared counter can
+// only be waited to zero); one word per lane, since the texture path bounds this loop.
+__device__ __forceinline__ uint32_t load_rec8(const Fp8Args& a, int b, int g, int lane) {
+  return reinterpret_cast<const uint32_t*>(a.rec)[((long long)b * kLaneGroups + g) * 4 + (lane & 3)];
+}
+
+// Word J of the lane group's record: lane 4q + J of each quad loaded it (quad_perm [J,J,J,J]).
+template <int J>
+__device__ __forceinline__ uint32_t rec8_word(uint32_t w) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x55 * J, 0xF, 0xF, false);
 }
 
 // LDS offsets of the lane group's four K-groups in an FP8 bundle (record words 0 and 1).
@@ -574,8 +581,9 @@ struct X8Offs {
   int o[4];
 };
 
-__device__ __forceinline__ X8Offs x8_offsets(const u32x4& r) {
-  return X8Offs{{(int)(r.x & 0xffff), (int)(r.x >> 16), (int)(r.y & 0xffff), (int)(r.y >> 16)}};
+__device__ __forceinline__ X8Offs x8_offsets(uint32_t w) {
+  const uint32_t r0 = rec8_word<0>(w), r1 = rec8_word<1>(w);
+  return X8Offs{{(int)(r0 & 0xffff), (int)(r0 >> 16), (int)(r1 & 0xffff), (int)(r1 >> 16)}};
 }
 
 // Position fragments of one FP8 bundle for the NT tiles of this lane: for each of the lane
@@ -672,13 +680,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     u32x4 pf[PF];
     int pf_off[PF];
     F8Frag ring[PD];
-    u32x4 rq[RQ];
+    uint32_t rq[RQ];
     {
       const int4 U = a.units[u0];
 #pragma unroll
       for (int j = 0; j < PD; ++j) load_f8(pack, min(U.z + j, U.w - 1), lane, ring[j]);
 #pragma unroll
-      for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(U.z + j, U.w - 1), g);
+      for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(U.z + j, U.w - 1), g, lane);
       stage_prefetch<uint8_t, RS, PF>(sa, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
       stage_rows<uint8_t, RS, PF>(sa, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
       __syncthreads();
@@ -704,16 +712,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       for (int b0 = U.z; b0 < U.w; b0 += RQ) {
 #pragma unroll
         for (int j = 0; j < RQ; ++j) {
-          const int sc = (int)rq[j].z;  // the lane group's block scale bytes
+          const int sc = (int)rec8_word<2>(rq[j]);  // the lane group's block scale bytes
           // the 16-row halves the bundle reaches: word 3 of lane group 0 (lane 0's record)
-          const int hm = b0 + j < U.w ? __builtin_amdgcn_readfirstlane((int)rq[j].w) : 0;
+          const int hm = b0 + j < U.w ? __builtin_amdgcn_readfirstlane((int)rec8_word<3>(rq[j])) : 0;
           const X8Offs on = x8_offsets(rq[(j + 1) % RQ]);
           __builtin_amdgcn_sched_barrier(0);
           read_x8<NT>(lds, lbase, on, (j % 2) ? xa : xb);
           __builtin_amdgcn_sched_barrier(0);
           fp8_mma<NT>(ring[j % PD], sc, hm, xs, (j % 2) ? xb : xa, acc);
           load_f8(pack, min(b0 + j + PD, U.w - 1), lane, ring[j % PD]);
-          rq[j] = load_rec8(a, min(b0 + j + RQ, U.w - 1), g);
+          rq[j] = load_rec8(a, min(b0 + j + RQ, U.w - 1), g, lane);
         }
       }
       if (u + 1 < u1) {
@@ -722,7 +730,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
         for (int j = 0; j < PD; ++j) load_f8(pack, min(Un.z + j, Un.w - 1), lane, ring[j]);
 #pragma unroll
-        for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(Un.z + j, Un.w - 1), g);
+        for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(Un.z + j, Un.w - 1), g, lane);
         const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
         if (!free_slot) __syncthreads();
         stage_rows<uint8_t, RS, PF>(sa, in, lds, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
