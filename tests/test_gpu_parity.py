@@ -439,16 +439,17 @@ def test_fista_bf16_anchored_matches_oracle(name, period, warmup):
 
 
 @pytest.mark.parametrize("name,period,warmup,tol", [("pairs16", 2, 100, 1e-4),
-                                                     ("mid7", 2, 45, 2e-4)])
+                                                     ("mid7", 2, 50, 1e-4)])
 def test_fista_fp8_anchored_matches_oracle(name, period, warmup, tol):
     """e4m3 correction applies with FP32 anchor gradients.  Between anchors the corrections
     2 A^T A (y - x_a) carry the FP8 apply error (3-6 % relative), and FISTA follows its
     trajectory with those errors, so plain FP8 FISTA ends about 1e-1 from the FP64 oracle.
     With FP32 gradients for the first half of the iterations and then at every second one,
-    the 200-iteration pairs run ends within 1e-4 of the oracle (150 of 200 gradients in FP32).
-    The 60-iteration mid7 run stays near 1.3e-4 even with 53 of 60 gradients in FP32 (the
-    FP8 error enters with the last iterations' large steps), so it is held to 2e-4; the BF16
-    anchored schedule meets 1e-4 on both."""
+    the 200-iteration pairs run ends within 1e-4 of the oracle (150 of 200 gradients in FP32,
+    measured 6.4e-5).  The 60-iteration mid7 run needs FP32 gradients for its first 50
+    iterations and then every second one (55 of 60) to reach 1e-4 (measured 9.9e-5; with 53
+    of 60, 1.3e-4): the FP8 error enters with the last iterations' still large steps, so on
+    so short a run FP8 saves little.  The BF16 anchored schedule meets 1e-4 on both."""
     m = gpu_model(name)
     iters = 200 if name == "pairs16" else 60
     s, L, lam, x_ref = _fista_ref(name, iters)
