@@ -513,20 +513,35 @@ __global__ void k_chunk_scales(const float* __restrict__ part, int nparts, int n
 }
 
 // Stage an FP32 input into the zero-padded e4m3 layout [nyp][nxp][Lp] (codes of x 2^-e of its
-// chunk); one workgroup per padded column, as k_stage.
-__global__ __launch_bounds__(256) void k_stage_fp8(const float* __restrict__ in,
-                                                   uint8_t* __restrict__ out,
-                                                   const float* __restrict__ xinv, int K, int nx,
-                                                   int ny, int nxp, int L, int Lp) {
+// chunk); one workgroup of 64 threads per padded column, each thread four consecutive entries
+// (one chunk, since Lp and the chunk are multiples of 4) written as one 32-bit word.  vec4: the
+// input rows are 16-byte aligned (L % 4 == 0 and an aligned base), so they load as float4.
+__global__ __launch_bounds__(64) void k_stage_fp8(const float* __restrict__ in,
+                                                  uint8_t* __restrict__ out,
+                                                  const float* __restrict__ xinv, int K, int nx,
+                                                  int ny, int nxp, int L, int Lp, int vec4) {
   const int col = blockIdx.x;
   const int px = col % nxp - K, py = col / nxp - K;
-  uint8_t* o = out + (long long)col * Lp;
+  uint32_t* o = reinterpret_cast<uint32_t*>(out + (long long)col * Lp);
   const bool inside = px >= 0 && px < nx && py >= 0 && py < ny;
   const float* src = in + ((long long)py * nx + px) * L;
-  for (int l = threadIdx.x; l < Lp; l += blockDim.x) {
-    uint8_t v = 0;
-    if (inside && l < L) v = f32_to_e4m3(src[l] * xinv[l / 64]);
-    o[l] = v;
+  for (int q = threadIdx.x; q < Lp / 4; q += blockDim.x) {
+    const int l0 = 4 * q;
+    uint32_t w = 0;
+    if (inside && l0 < L) {
+      float v[4];
+      if (vec4) {
+        const float4 f = *reinterpret_cast<const float4*>(src + l0);
+        v[0] = f.x, v[1] = f.y, v[2] = f.z, v[3] = f.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = l0 + i < L ? src[l0 + i] : 0.0f;
+      }
+      const float sc = xinv[l0 / 64];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w |= (uint32_t)f32_to_e4m3(v[i] * sc) << (8 * i);
+    }
+    o[q] = w;
   }
 }
 
@@ -783,7 +798,7 @@ size_t elem_bytes(int dtype) {
   }
 }
 
-constexpr int kAmaxParts = 64;  // position slices of the FP8 operand's chunk maxima
+constexpr int kAmaxParts = 512;  // position slices of the FP8 operand's chunk maxima
 
 }  // namespace
 
@@ -919,8 +934,10 @@ int launch_fp8(const Model& m, const Layout& lay, const Pack& pk, const float* i
                      npos, pg.L, amax);
   hipLaunchKernelGGL(k_chunk_scales, dim3((unsigned)ceil_div(sp.chunks, 64)), dim3(64), 0, st,
                      (const float*)amax, kAmaxParts, sp.chunks, xexp, xinv);
-  hipLaunchKernelGGL(k_stage_fp8, dim3((unsigned)(pg.nyp * pg.nxp)), dim3(256), 0, st, in, staged,
-                     (const float*)xinv, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp);
+  AROAM_CHECK(pg.Lp % 64 == 0, AROAM_EINVAL, "FP8 staging needs whole 64-entry chunks");
+  const int vec4 = pg.L % 4 == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0;
+  hipLaunchKernelGGL(k_stage_fp8, dim3((unsigned)(pg.nyp * pg.nxp)), dim3(64), 0, st, in, staged,
+                     (const float*)xinv, pg.K, pg.nx, pg.ny, pg.nxp, pg.L, pg.Lp, vec4);
   Fp8Args a;
   a.pieces = lay.d_pieces;
   a.tile_split = lay.d_tile_split;
