@@ -279,14 +279,14 @@ __device__ __forceinline__ void fp32_unit_bundles(const float* lds, const int (&
   }
 }
 
-// LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 rows) and one patch
-// of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT 16-position
-// tiles.  The tile's bundles are grouped into stage units (chunk, input row offset).  The LDS
-// holds the BR input rows a unit reads (all BC + 2K columns, the chunk's CH inner entries)
-// plus one free row, as a ring of BR + 1 slots indexed by padded row: a unit loads only the
-// rows it adds to the ring, and those rows are fetched into registers while the previous
-// unit computes.  Table fragments stream through a
-// PD-deep register ring that runs across unit boundaries.  Lane (n = lane % 16,
+// LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 MH rows) and one
+// patch of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT
+// 16-position tiles.  The tile's bundles are grouped into stage units (chunk, input row
+// offset).  The LDS holds the BR input rows a unit reads (all BC + 2K columns, the chunk's CH
+// inner entries) plus one free row, as a ring of BR + 1 slots indexed by padded row: a unit
+// loads only the rows it adds to the ring, and those rows are fetched into registers while
+// the previous unit computes.  Table fragments stream through a PD-deep register ring, whose
+// refill for the next unit is issued before that unit's rows are staged.  Lane (n = lane % 16,
 // g = lane / 16) holds row n of K-group g of the table and the entries of K-group g for
 // position n.
 // Two waves per SIMD (the LDS holds two workgroups of the 81 x 81 footprint): with that
@@ -367,8 +367,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           fp32_unit_bundles<MH, NT, TPR, TPR, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
         }
       } else {
-        // BF16: one register set for the position fragments (a second one would cost
-        // the third wave per SIMD, or a shorter table ring, both measured slower)
+        // BF16: one register set for the position fragments (a second one measured slower)
         for (int b0 = U.z; b0 < U.w; b0 += PD) {
 #pragma unroll
           for (int j = 0; j < PD; ++j) {
