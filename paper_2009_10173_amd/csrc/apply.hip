@@ -279,8 +279,8 @@ __device__ __forceinline__ void fp32_unit_bundles(const float* lds, const int (&
   }
 }
 
-// LDS-staged MFMA kernel.  A workgroup (4 waves) owns one output tile (16 MH rows) and one
-// patch of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT
+// LDS-staged FP32 MFMA kernel.  A workgroup (4 waves) owns one output tile (16 MH rows) and
+// one patch of BR scan rows x BC scan columns; each wave owns BR/4 rows x BC columns = NT
 // 16-position tiles.  The tile's bundles are grouped into stage units (chunk, input row
 // offset).  The LDS holds the BR input rows a unit reads (all BC + 2K columns, the chunk's CH
 // inner entries) plus one free row, as a ring of BR + 1 slots indexed by padded row: a unit
@@ -298,6 +298,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                       float* __restrict__ out, StagedArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
+  static_assert(sizeof(T) == 4, "the staged kernel is the FP32 path");
   constexpr int VEC = 16 / sizeof(T);  // entries per 16-byte vector == K-group width G
   constexpr int TPR = BC / 16;
   constexpr int RW = BR / 4;
@@ -350,35 +351,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
         lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
       }
-      // FP32: a wave whose rows read only the zero rows around the scan grid at this unit's
-      // row offset skips the unit's MFMAs (it still stages its share of the unit's rows).  The
-      // BF16 loop, compiled with that branch, ran slower than it gains.
+      // a wave whose rows read only the zero rows around the scan grid at this unit's row
+      // offset skips the unit's MFMAs (it still stages its share of the unit's rows)
       const int src_row = py0 + wave * RW + U.x;
-      const bool live = sizeof(T) != 4 || (src_row + RW > 0 && src_row < a.ny);
+      const bool live = src_row + RW > 0 && src_row < a.ny;
       if (!live) {
-      } else if constexpr (sizeof(T) == 4) {
+      } else if constexpr (TPR == 2) {
         // a patch at the grid's last columns computes only its tiles that hold scan columns
-        if constexpr (TPR == 2) {
-          if (px0 + 16 >= a.nx)
-            fp32_unit_bundles<MH, NT, TPR, 1, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
-          else
-            fp32_unit_bundles<MH, NT, TPR, TPR, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
-        } else {
+        if (px0 + 16 >= a.nx)
+          fp32_unit_bundles<MH, NT, TPR, 1, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
+        else
           fp32_unit_bundles<MH, NT, TPR, TPR, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
-        }
       } else {
-        // BF16: one register set for the position fragments (a second one measured slower)
-        for (int b0 = U.z; b0 < U.w; b0 += PD) {
-#pragma unroll
-          for (int j = 0; j < PD; ++j) {
-            if (b0 + j < U.w) {
-              u32x4 x[NT];
-              read_x<T, NT>(lds, lbase, ring[j].mo, x);
-              bundle_mma<T, MH, NT>(ring[j], x, acc);
-            }
-            load_a<T, MH>(pack_raw, a.meta, min(b0 + j + PD, U.w - 1), g, n, ring[j]);
-          }
-        }
+        fp32_unit_bundles<MH, NT, TPR, TPR, PD>(lds, lbase, ring, acc, pack_raw, a, U, g, n);
       }
       if (u + 1 < u1) {
         const int4 Un = a.units[u + 1];
@@ -420,6 +405,141 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
   }
 }
+
+// Waves that share a BF16 stage unit's bundle stream (the split kernel's S).
+constexpr int kSplit = 4;
+
+// BF16 staged kernel with each stage unit's bundle stream split over waves.  The four waves
+// of a workgroup form 4 / S row groups of the BR x BC patch, and the S waves of a row group
+// take every S-th bundle of each unit, so each wave holds NT = BR * BC / (16 * 4 / S)
+// position tiles and every table fragment is loaded once per row group (S times fewer table
+// loads through the texture-address path per MFMA than with S = 1).  Staging and the LDS row
+// ring are those of k_apply_staged.  At the end the S partial sums of a position are added in
+// wave order through the LDS, in phases of S tiles (red_bytes() of LDS).
+template <int BR, int BC, int MH, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply_split(
+    const void* __restrict__ pack_raw, const uint16_t* __restrict__ in, float* __restrict__ out,
+    StagedArgs a) {
+  using T = uint16_t;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  constexpr int VEC = 8;
+  constexpr int TPR = BC / 16;
+  constexpr int P = 4 / S;      // row groups
+  constexpr int RW = BR / P;    // patch rows per wave
+  constexpr int NT = RW * TPR;  // 16-position tiles per wave
+  static_assert(4 % S == 0 && BR % P == 0 && NT % S == 0, "split shape");
+  constexpr int PF = 2;         // prefetched stage vectors per thread
+  constexpr int PD = 2;         // table-fragment ring depth
+  constexpr int CH = 4 * VEC;
+  const int4 piece = a.pieces[blockIdx.y];
+  const int tile = piece.x;
+  const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int grp = wave / S, sw = wave % S;
+  const int n = lane % 16, g = lane / 16;
+  constexpr int nvec = CH / VEC;
+  const int rowvec = a.NCOL * nvec;
+  floatx4 acc[MH][NT];
+#pragma unroll
+  for (int h = 0; h < MH; ++h)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[h][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int u0 = piece.y, u1 = piece.z;
+  if (u0 < u1) {
+    constexpr int RS = BR + 1;
+    u32x4 pf[PF];
+    int pf_off[PF];
+    AFrag<T, MH> ring[PD];
+    {
+      const int4 U = a.units[u0];
+#pragma unroll
+      for (int j = 0; j < PD; ++j)
+        load_a<T, MH>(pack_raw, a.meta, min(U.z + sw + S * j, U.w - 1), g, n, ring[j]);
+      stage_prefetch<T, RS, PF>(a, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
+      stage_rows<T, RS, PF>(a, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
+      __syncthreads();
+      if (u0 + 1 < u1)
+        stage_prefetch<T, RS, PF>(a, in, u0 + 1, py0, px0, rowvec, nvec, pf, pf_off);
+    }
+    for (int u = u0; u < u1; ++u) {
+      const int4 U = a.units[u];
+      const int R = U.x + a.K;
+      int lbase[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int r = grp * RW + t / TPR, c = (t % TPR) * 16 + n;
+        lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
+      }
+      for (int b0 = U.z + sw; b0 < U.w; b0 += S * PD) {
+#pragma unroll
+        for (int j = 0; j < PD; ++j) {
+          const int b = b0 + S * j;
+          if (b < U.w) {
+            u32x4 x[NT];
+            read_x<T, NT>(lds, lbase, ring[j].mo, x);
+            bundle_mma<T, MH, NT>(ring[j], x, acc);
+          }
+          load_a<T, MH>(pack_raw, a.meta, min(b + S * PD, U.w - 1), g, n, ring[j]);
+        }
+      }
+      if (u + 1 < u1) {
+        const int4 Un = a.units[u + 1];
+        const int2 Rn = a.urows[u + 1];
+#pragma unroll
+        for (int j = 0; j < PD; ++j)
+          load_a<T, MH>(pack_raw, a.meta, min(Un.z + sw + S * j, Un.w - 1), g, n, ring[j]);
+        const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
+        if (!free_slot) __syncthreads();
+        stage_rows<T, RS, PF>(a, in, lds, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
+        __syncthreads();
+        if (u + 2 < u1)
+          stage_prefetch<T, RS, PF>(a, in, u + 2, py0, px0, rowvec, nvec, pf, pf_off);
+      }
+    }
+  }
+  constexpr int PS = BR * BC * 16 * MH;  // floats per slot and patch
+  float* slot =
+      piece.w >= 0 ? a.partial + ((long long)piece.w * a.n_patches + blockIdx.x) * PS : nullptr;
+  // partial sums of the S waves of a row group, S tiles per phase: wave sw of the group adds
+  // tile p + sw over the group's waves (in wave order) and writes it
+  floatx4* red = reinterpret_cast<floatx4*>(lds_raw);
+  __syncthreads();  // every wave is done with the row ring
+#pragma unroll
+  for (int p = 0; p < NT; p += S) {
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+#pragma unroll
+      for (int h = 0; h < MH; ++h) red[((wave * S + k) * MH + h) * 64 + lane] = acc[h][p + k];
+    __syncthreads();
+    floatx4 v[MH];
+#pragma unroll
+    for (int h = 0; h < MH; ++h) {
+      v[h] = red[(((grp * S) * S + sw) * MH + h) * 64 + lane];
+#pragma unroll
+      for (int s = 1; s < S; ++s) v[h] += red[(((grp * S + s) * S + sw) * MH + h) * 64 + lane];
+    }
+    const int t = p + sw;
+    const int py = py0 + grp * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
+    if (py < a.ny && px < a.nx) {
+      const int local = (grp * RW + t / TPR) * BC + (t % TPR) * 16 + n;
+      float* dst = slot ? slot : out;
+      const long long off = slot ? (long long)local * (16 * MH) - 16 * MH * tile
+                                 : ((long long)py * a.nx + px) * a.out_len;
+#pragma unroll
+      for (int h = 0; h < MH; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * MH * tile + 16 * h + 4 * g + i;
+          if (row < a.out_len) dst[off + row] = v[h][i];
+        }
+    }
+    __syncthreads();  // the next phase overwrites the sums
+  }
+}
+
+// LDS bytes of the split kernel's final sums: S tiles of MH halves per wave, four waves.
+constexpr size_t red_bytes(int S, int MH) { return (size_t)4 * S * MH * 64 * 16; }
 
 // Output of the cut tiles: the sum of a tile's partial slots in slot order (the order of the
 // tile's stage units), written like the staged kernel's own output.  Grid: (patch, tile);
@@ -600,83 +720,81 @@ __device__ __forceinline__ X8Offs x8_offsets(uint32_t w) {
   return X8Offs{{(int)(r0 & 0xffff), (int)(r0 >> 16), (int)(r1 & 0xffff), (int)(r1 >> 16)}};
 }
 
-// Position fragments of one FP8 bundle for the NT tiles of this lane: for each of the lane
-// group's four K-groups, 8 bytes of the lane's position from the LDS.
-template <int NT>
-__device__ __forceinline__ void read_x8(const uint8_t* lds, const int (&lbase)[NT], const X8Offs& o,
-                                        u32x4 (&x)[NT][2]) {
+// Position fragments of one FP8 bundle for tiles [t0, t0 + NX) of this lane: for each of the
+// lane group's four K-groups, 8 bytes of the lane's position from the LDS.  Tile t sits at row
+// base rb[t / TPR] plus column offset (t % TPR) * cstep.  The step is a run-time value: as an
+// immediate, the compiler pairs the reads of neighbouring tiles into one instruction whose
+// registers then have to be moved into each MFMA's operand order.
+template <int TPR, int NX, int NR>
+__device__ __forceinline__ void read_x8(const uint8_t* lds, const int (&rb)[NR], int cstep, int t0,
+                                         const X8Offs& o, u32x4 (&x)[NX][2]) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const u32x2 q0 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[0]);
-    const u32x2 q1 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[1]);
-    const u32x2 q2 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[2]);
-    const u32x2 q3 = *reinterpret_cast<const u32x2*>(lds + lbase[t] + o.o[3]);
-    x[t][0] = u32x4{q0.x, q0.y, q1.x, q1.y};
-    x[t][1] = u32x4{q2.x, q2.y, q3.x, q3.y};
+  for (int i = 0; i < NX; ++i) {
+    const int t = t0 + i;
+    const uint8_t* p = lds + rb[t / TPR] + (t % TPR) * cstep;
+    const u32x2 q0 = *reinterpret_cast<const u32x2*>(p + o.o[0]);
+    const u32x2 q1 = *reinterpret_cast<const u32x2*>(p + o.o[1]);
+    const u32x2 q2 = *reinterpret_cast<const u32x2*>(p + o.o[2]);
+    const u32x2 q3 = *reinterpret_cast<const u32x2*>(p + o.o[3]);
+    x[i][0] = u32x4{q0.x, q0.y, q1.x, q1.y};
+    x[i][1] = u32x4{q2.x, q2.y, q3.x, q3.y};
   }
 }
 
-// The block-scaled MFMAs of one FP8 bundle: per reached half h (bit h of hm) and position tile,
-// 16 rows x 128 K x 16 positions, with the lane's block scale byte h of sc and the unit's
-// operand scale xs.
-template <int NT>
-__device__ __forceinline__ void fp8_mma(const F8Frag& f, int sc, int hm, int xs,
-                                        const u32x4 (&x)[NT][2], floatx4 (&acc)[2][NT]) {
-  if (hm & 1) {
-    const intx8 av = __builtin_bit_cast(
-        intx8, u32x8{f.v[0][0].x, f.v[0][0].y, f.v[0][0].z, f.v[0][0].w, f.v[0][1].x, f.v[0][1].y,
-                     f.v[0][1].z, f.v[0][1].w});
+// The block-scaled MFMAs of half H of one FP8 bundle for tiles [t0, t0 + NX) (t0 a constant
+// after unrolling) whose fragments are x[0 .. NX): 16 rows x 128 K x 16 positions each, with
+// the lane's block scale byte H of sc and the unit's operand scale xs.
+template <int H, int NT, int NX>
+__device__ __forceinline__ void fp8_mma_h(const F8Frag& f, int sc, int xs, int t0,
+                                          const u32x4 (&x)[NX][2], floatx4 (&acc)[2][NT]) {
+  const intx8 av = __builtin_bit_cast(
+      intx8, u32x8{f.v[H][0].x, f.v[H][0].y, f.v[H][0].z, f.v[H][0].w, f.v[H][1].x, f.v[H][1].y,
+                   f.v[H][1].z, f.v[H][1].w});
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const intx8 bv = __builtin_bit_cast(intx8, u32x8{x[t][0].x, x[t][0].y, x[t][0].z, x[t][0].w,
-                                                       x[t][1].x, x[t][1].y, x[t][1].z, x[t][1].w});
-      acc[0][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[0][t], 0, 0, 0, sc,
-                                                                   0, xs);
-    }
-  }
-  if (hm & 2) {
-    const intx8 av = __builtin_bit_cast(
-        intx8, u32x8{f.v[1][0].x, f.v[1][0].y, f.v[1][0].z, f.v[1][0].w, f.v[1][1].x, f.v[1][1].y,
-                     f.v[1][1].z, f.v[1][1].w});
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const intx8 bv = __builtin_bit_cast(intx8, u32x8{x[t][0].x, x[t][0].y, x[t][0].z, x[t][0].w,
-                                                       x[t][1].x, x[t][1].y, x[t][1].z, x[t][1].w});
-      acc[1][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[1][t], 0, 0, 1, sc,
-                                                                   0, xs);
-    }
+  for (int i = 0; i < NX; ++i) {
+    const intx8 bv = __builtin_bit_cast(intx8, u32x8{x[i][0].x, x[i][0].y, x[i][0].z, x[i][0].w,
+                                                     x[i][1].x, x[i][1].y, x[i][1].z, x[i][1].w});
+    acc[H][t0 + i] =
+        __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[H][t0 + i], 0, 0, H, sc, 0, xs);
   }
 }
 
-// LDS-staged FP8 kernel: the staged kernel's workgroup shape, LDS row ring and unit order
-// (BR x BC position patch, 32-row tile of two 16-row halves, NT 16-position tiles per wave),
-// with bundles of 16 K-groups: per half and position tile one block-scaled MFMA of K = 128.
-// Lane (n, g) reads, for each of its lane group's four K-groups, 8 bytes of position n from
-// the LDS (the K-group's column and run) and 32 bytes of table row n per half.
-// Two waves per SIMD: the 160 KiB LDS holds at most two workgroups of the 81 x 81 footprint
-// (K = 40) anyway, and the larger register budget keeps the table stage's next-row fetch and
-// the ring's loads counted (no full vmcnt wait per bundle).
-template <int BR, int BC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply_fp8(const uint8_t* __restrict__ pack,
-                                                   const uint8_t* __restrict__ in,
-                                                   float* __restrict__ out, Fp8Args a) {
+// FP8 split kernel shape: waves sharing a unit's bundle stream, position-fragment read phases
+// per bundle, table-fragment ring depth.
+constexpr int kSplit8 = 4, kPhases8 = 4, kRing8 = 1;
+
+// LDS-staged FP8 kernel: the BF16 split kernel's workgroup shape, LDS row ring, unit order and
+// bundle split (4 / S row groups of the BR x BC patch; the S waves of a row group take every
+// S-th bundle of each stage unit; the S partial sums of a position are added in wave order
+// through the LDS at the end), with bundles of 16 K-groups: per reached 16-row half and
+// position tile one block-scaled MFMA of K = 128.  Lane (n, g) reads, for each of its lane
+// group's four K-groups, 8 bytes of position n from the LDS (the K-group's column and run) and
+// 32 bytes of table row n per half.  An FP8 position fragment takes 8 VGPRs, so a wave reads
+// its NT fragments in XP phases; the table ring is PD bundles deep.
+template <int BR, int BC, int S, int XP, int PD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply_fp8s(
+    const uint8_t* __restrict__ pack, const uint8_t* __restrict__ in, float* __restrict__ out,
+    Fp8Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   uint8_t* lds = lds_raw;
   constexpr int TPR = BC / 16;
-  constexpr int RW = BR / 4;
+  constexpr int P = 4 / S;
+  constexpr int RW = BR / P;
   constexpr int NT = RW * TPR;
-  constexpr int PF = 4;
-  constexpr int PD = 2;                // table-fragment ring depth (bundles)
-  constexpr int RQ = 4;                // record ring depth (bundles; a multiple of PD)
+  static_assert(4 % S == 0 && BR % P == 0 && NT % S == 0 && NT % XP == 0, "split shape");
+  constexpr int NX = NT / XP;          // tiles per position-fragment read phase
+  constexpr int PF = 2;
+  constexpr int RQ = 4;                // record ring depth (a multiple of PD)
   constexpr int MH = 2;
   const int4 piece = a.pieces[blockIdx.y];
   const int tile = piece.x;
   const int py0 = (blockIdx.x / a.ncc) * BR, px0 = (blockIdx.x % a.ncc) * BC;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int grp = wave / S, sw = wave % S;
   const int n = lane % 16, g = lane / 16;
-  constexpr int nvec = 4;              // 16-byte vectors per staged column (64-byte chunk)
+  constexpr int nvec = 4;
   const int rowvec = a.NCOL * nvec;
-  StagedArgs sa;                       // the staging helpers' view of the arguments
+  StagedArgs sa;
   sa.units = a.units;
   sa.urows = a.urows;
   sa.NCOL = a.NCOL;
@@ -698,79 +816,96 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     {
       const int4 U = a.units[u0];
 #pragma unroll
-      for (int j = 0; j < PD; ++j) load_f8(pack, min(U.z + j, U.w - 1), lane, ring[j]);
+      for (int j = 0; j < PD; ++j) load_f8(pack, min(U.z + sw + S * j, U.w - 1), lane, ring[j]);
 #pragma unroll
-      for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(U.z + j, U.w - 1), g, lane);
+      for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(U.z + sw + S * j, U.w - 1), g, lane);
       stage_prefetch<uint8_t, RS, PF>(sa, in, u0, py0, px0, rowvec, nvec, pf, pf_off);
       stage_rows<uint8_t, RS, PF>(sa, in, lds, u0, py0, px0, rowvec, nvec, pf, pf_off);
       __syncthreads();
-      if (u0 + 1 < u1) stage_prefetch<uint8_t, RS, PF>(sa, in, u0 + 1, py0, px0, rowvec, nvec, pf, pf_off);
+      if (u0 + 1 < u1)
+        stage_prefetch<uint8_t, RS, PF>(sa, in, u0 + 1, py0, px0, rowvec, nvec, pf, pf_off);
     }
     for (int u = u0; u < u1; ++u) {
       const int4 U = a.units[u];
-      const int xs = a.xexp[U.y / 64];  // the unit's chunk: one operand scale
+      const int xs = a.xexp[U.y / 64];
       const int R = U.x + a.K;
-      int lbase[NT];
+      int rb[RW];  // LDS base of this lane's position in each of the wave's rows
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int r = wave * RW + t / TPR, c = (t % TPR) * 16 + n;
-        lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
-      }
-      // The next bundle's position fragments are read while this bundle's MFMAs run (two
-      // register sets).  Table slot j mod PD holds bundle b0 + j, record slot j bundle b0 + j
-      // (or clamped copies of the unit's last bundle); records are loaded RQ bundles ahead,
-      // since the next bundle's LDS offsets are needed a bundle before its table fragments.
-      // The scheduling barriers keep the next bundle's reads ahead of this bundle's MFMAs.
-      u32x4 xa[NT][2], xb[NT][2];
-      read_x8<NT>(lds, lbase, x8_offsets(rq[0]), xa);
-      for (int b0 = U.z; b0 < U.w; b0 += RQ) {
+      for (int r = 0; r < RW; ++r) rb[r] = (((grp * RW + r + R) % RS) * a.NCOL + n) * a.CS;
+      const int cstep = 16 * a.CS;
+      for (int b0 = U.z + sw; b0 < U.w; b0 += S * RQ) {
 #pragma unroll
         for (int j = 0; j < RQ; ++j) {
-          const int sc = (int)rec8_word<2>(rq[j]);  // the lane group's block scale bytes
-          // the 16-row halves the bundle reaches: word 3 of lane group 0 (lane 0's record)
-          const int hm = b0 + j < U.w ? __builtin_amdgcn_readfirstlane((int)rec8_word<3>(rq[j])) : 0;
-          const X8Offs on = x8_offsets(rq[(j + 1) % RQ]);
-          __builtin_amdgcn_sched_barrier(0);
-          read_x8<NT>(lds, lbase, on, (j % 2) ? xa : xb);
-          __builtin_amdgcn_sched_barrier(0);
-          fp8_mma<NT>(ring[j % PD], sc, hm, xs, (j % 2) ? xb : xa, acc);
-          load_f8(pack, min(b0 + j + PD, U.w - 1), lane, ring[j % PD]);
-          rq[j] = load_rec8(a, min(b0 + j + RQ, U.w - 1), g, lane);
+          const int b = b0 + S * j;
+          const int sc = (int)rec8_word<2>(rq[j]);
+          const int hm = b < U.w ? __builtin_amdgcn_readfirstlane((int)rec8_word<3>(rq[j])) : 0;
+          if (hm) {
+            const X8Offs o = x8_offsets(rq[j]);
+#pragma unroll
+            for (int ph = 0; ph < XP; ++ph) {
+              u32x4 x[NX][2];
+              read_x8<TPR, NX>(lds, rb, cstep, ph * NX, o, x);
+              if (hm & 1) fp8_mma_h<0, NT, NX>(ring[j % PD], sc, xs, ph * NX, x, acc);
+              if (hm & 2) fp8_mma_h<1, NT, NX>(ring[j % PD], sc, xs, ph * NX, x, acc);
+            }
+          }
+          load_f8(pack, min(b + S * PD, U.w - 1), lane, ring[j % PD]);
+          rq[j] = load_rec8(a, min(b + S * RQ, U.w - 1), g, lane);
         }
       }
       if (u + 1 < u1) {
         const int4 Un = a.units[u + 1];
         const int2 Rn = a.urows[u + 1];
 #pragma unroll
-        for (int j = 0; j < PD; ++j) load_f8(pack, min(Un.z + j, Un.w - 1), lane, ring[j]);
+        for (int j = 0; j < PD; ++j)
+          load_f8(pack, min(Un.z + sw + S * j, Un.w - 1), lane, ring[j]);
 #pragma unroll
-        for (int j = 0; j < RQ; ++j) rq[j] = load_rec8(a, min(Un.z + j, Un.w - 1), g, lane);
+        for (int j = 0; j < RQ; ++j)
+          rq[j] = load_rec8(a, min(Un.z + sw + S * j, Un.w - 1), g, lane);
         const bool free_slot = Rn.y - Rn.x == 1 && Rn.x == R + BR;
         if (!free_slot) __syncthreads();
         stage_rows<uint8_t, RS, PF>(sa, in, lds, u + 1, py0, px0, rowvec, nvec, pf, pf_off);
         __syncthreads();
-        if (u + 2 < u1) stage_prefetch<uint8_t, RS, PF>(sa, in, u + 2, py0, px0, rowvec, nvec, pf, pf_off);
+        if (u + 2 < u1)
+          stage_prefetch<uint8_t, RS, PF>(sa, in, u + 2, py0, px0, rowvec, nvec, pf, pf_off);
       }
     }
   }
   constexpr int PS = BR * BC * 16 * MH;
   float* slot =
       piece.w >= 0 ? a.partial + ((long long)piece.w * a.n_patches + blockIdx.x) * PS : nullptr;
+  floatx4* red = reinterpret_cast<floatx4*>(lds_raw);
+  __syncthreads();
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int py = py0 + wave * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
-    if (py >= a.ny || px >= a.nx) continue;
-    const int local = (wave * RW + t / TPR) * BC + (t % TPR) * 16 + n;
-    float* dst = slot ? slot : out;
-    const long long off = slot ? (long long)local * (16 * MH) - 16 * MH * tile
-                               : ((long long)py * a.nx + px) * a.out_len;
+  for (int p = 0; p < NT; p += S) {
 #pragma unroll
-    for (int h = 0; h < MH; ++h)
+    for (int k = 0; k < S; ++k)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * MH * tile + 16 * h + 4 * g + i;
-        if (row < a.out_len) dst[off + row] = acc[h][t][i];
-      }
+      for (int h = 0; h < MH; ++h) red[((wave * S + k) * MH + h) * 64 + lane] = acc[h][p + k];
+    __syncthreads();
+    floatx4 v[MH];
+#pragma unroll
+    for (int h = 0; h < MH; ++h) {
+      v[h] = red[(((grp * S) * S + sw) * MH + h) * 64 + lane];
+#pragma unroll
+      for (int s = 1; s < S; ++s) v[h] += red[(((grp * S + s) * S + sw) * MH + h) * 64 + lane];
+    }
+    const int t = p + sw;
+    const int py = py0 + grp * RW + t / TPR, px = px0 + (t % TPR) * 16 + n;
+    if (py < a.ny && px < a.nx) {
+      const int local = (grp * RW + t / TPR) * BC + (t % TPR) * 16 + n;
+      float* dst = slot ? slot : out;
+      const long long off = slot ? (long long)local * (16 * MH) - 16 * MH * tile
+                                 : ((long long)py * a.nx + px) * a.out_len;
+#pragma unroll
+      for (int h = 0; h < MH; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * MH * tile + 16 * h + 4 * g + i;
+          if (row < a.out_len) dst[off + row] = v[h][i];
+        }
+    }
+    __syncthreads();
   }
 }
 
@@ -843,25 +978,24 @@ size_t stage_bytes(const Model& m, bool adjoint, int dtype) {
 
 namespace {
 
-template <typename T, int MH>
-int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* partial, void* out,
-                  hipStream_t st) {
-  static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
-  AROAM_CHECK(lay.TM == 16 * MH, AROAM_EINVAL, "tile height mismatch");
-  auto kern = k_apply_staged<T, kPatchRows, kPatchCols, MH>;
-  // allow the full LDS of a CU for wide footprints, once per device
-  static std::atomic<unsigned long long> attr_set{0};
+// Allow the full LDS of a CU for a kernel, once per device.
+template <typename F>
+int allow_full_lds(F kern, std::atomic<unsigned long long>& done) {
   int dev = 0;
   AROAM_HIP(hipGetDevice(&dev));
   const unsigned long long bit = 1ull << (dev & 63);
-  if (!(attr_set.load() & bit)) {
+  if (!(done.load() & bit)) {
     AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)kLdsBytes));
-    attr_set.fetch_or(bit);
+    done.fetch_or(bit);
   }
+  return AROAM_OK;
+}
+
+// Arguments of the staged kernels for a layout (and the partial slots of its cut tiles).
+int staged_args(const Layout& lay, float* partial, int elem_size, StagedArgs& a) {
   AROAM_CHECK(lay.lds_bytes <= kLdsBytes, AROAM_EINVAL,
               "lateral footprint too wide for the LDS stage (%zu bytes)", lay.lds_bytes);
-  StagedArgs a;
   a.pieces = lay.d_pieces;
   a.tile_split = lay.d_tile_split;
   a.partial = partial;
@@ -878,10 +1012,45 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
   a.ncc = (int)ceil_div(lay.in.nx, kPatchCols);
   a.NCOL = lay.NCOL;
   a.CS = lay.CS;
-  AROAM_CHECK(lay.CH == 4 * (int)(16 / sizeof(T)), AROAM_EINVAL, "chunk length mismatch");
+  AROAM_CHECK(lay.CH == 4 * (16 / elem_size), AROAM_EINVAL, "chunk length mismatch");
   AROAM_CHECK(lay.n_patches == ceil_div(lay.in.ny, kPatchRows) * a.ncc, AROAM_EINVAL,
               "patch count mismatch");
   AROAM_CHECK(lay.n_slots == 0 || partial, AROAM_EINVAL, "no partial slots for a cut layout");
+  return AROAM_OK;
+}
+
+// BF16 apply: the split kernel, then the slot sums of cut tiles.
+template <int MH>
+int launch_split(const Layout& lay, const Pack& pk, const void* buf, float* partial, void* out,
+                 hipStream_t st) {
+  AROAM_CHECK(lay.TM == 16 * MH, AROAM_EINVAL, "tile height mismatch");
+  auto kern = k_apply_split<kPatchRows, kPatchCols, MH, kSplit>;
+  static std::atomic<unsigned long long> attr_set{0};
+  AROAM_TRY(allow_full_lds(kern, attr_set));
+  StagedArgs a;
+  AROAM_TRY(staged_args(lay, partial, 2, a));
+  const size_t lds = std::max(lay.lds_bytes, red_bytes(kSplit, MH));
+  const dim3 grid((unsigned)lay.n_patches, (unsigned)lay.n_pieces);
+  hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, (const void*)pk.d, (const uint16_t*)buf,
+                     (float*)out, a);
+  if (lay.n_slots > 0)
+    hipLaunchKernelGGL((k_add_slots<kPatchRows, kPatchCols, MH>),
+                       dim3((unsigned)lay.n_patches, (unsigned)lay.n_tiles), dim3(256), 0, st,
+                       lay.d_tile_split, (const float*)partial, (float*)out, lay.n_patches, a.ncc,
+                       a.nx, a.ny, a.out_len);
+  return AROAM_OK;
+}
+
+template <typename T, int MH>
+int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* partial, void* out,
+                  hipStream_t st) {
+  static_assert(kPatchRows % 4 == 0 && kPatchCols % 16 == 0, "patch shape");
+  AROAM_CHECK(lay.TM == 16 * MH, AROAM_EINVAL, "tile height mismatch");
+  auto kern = k_apply_staged<T, kPatchRows, kPatchCols, MH>;
+  static std::atomic<unsigned long long> attr_set{0};
+  AROAM_TRY(allow_full_lds(kern, attr_set));
+  StagedArgs a;
+  AROAM_TRY(staged_args(lay, partial, (int)sizeof(T), a));
   const dim3 grid((unsigned)lay.n_patches, (unsigned)lay.n_pieces);
   hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const void*)pk.d, (const T*)buf,
                      (float*)out, a);
@@ -897,26 +1066,11 @@ int launch_staged(const Layout& lay, const Pack& pk, const void* buf, float* par
 
 namespace {
 
-// The launches of one apply into the stage buffer `buf` (stage_bytes() bytes).
-// Allow the full LDS of a CU for a kernel, once per device.
-template <typename F>
-int allow_full_lds(F kern, std::atomic<unsigned long long>& done) {
-  int dev = 0;
-  AROAM_HIP(hipGetDevice(&dev));
-  const unsigned long long bit = 1ull << (dev & 63);
-  if (!(done.load() & bit)) {
-    AROAM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kLdsBytes));
-    done.fetch_or(bit);
-  }
-  return AROAM_OK;
-}
-
 // FP8 apply: chunk maxima and scales of the operand, the e4m3 staging, the staged FP8 kernel,
 // and the slot sums of cut tiles.
 int launch_fp8(const Model& m, const Layout& lay, const Pack& pk, const float* in, void* buf,
                const StageParts& sp, void* out, hipStream_t st) {
-  auto kern = k_apply_fp8<kPatchRows, kPatchCols>;
+  auto kern = k_apply_fp8s<kPatchRows, kPatchCols, kSplit8, kPhases8, kRing8>;
   static std::atomic<unsigned long long> attr_set{0};
   AROAM_TRY(allow_full_lds(kern, attr_set));
   AROAM_CHECK(lay.TM == kTileRows8 && lay.CH == 64 && lay.CS == kColumnBytes, AROAM_EINVAL,
@@ -959,8 +1113,8 @@ int launch_fp8(const Model& m, const Layout& lay, const Pack& pk, const float* i
               "patch count mismatch");
   AROAM_CHECK(lay.n_slots == 0 || partial, AROAM_EINVAL, "no partial slots for a cut layout");
   const dim3 grid((unsigned)lay.n_patches, (unsigned)lay.n_pieces);
-  hipLaunchKernelGGL(kern, grid, dim3(256), lay.lds_bytes, st, (const uint8_t*)pk.d,
-                     (const uint8_t*)staged, (float*)out, a);
+  hipLaunchKernelGGL(kern, grid, dim3(256), std::max(lay.lds_bytes, red_bytes(kSplit8, 2)), st,
+                     (const uint8_t*)pk.d, (const uint8_t*)staged, (float*)out, a);
   if (lay.n_slots > 0)
     hipLaunchKernelGGL((k_add_slots<kPatchRows, kPatchCols, 2>),
                        dim3((unsigned)lay.n_patches, (unsigned)lay.n_tiles), dim3(256), 0, st,
@@ -969,6 +1123,7 @@ int launch_fp8(const Model& m, const Layout& lay, const Pack& pk, const float* i
   return AROAM_OK;
 }
 
+// The launches of one apply into the stage buffer `buf` (stage_bytes() bytes).
 int launch_apply(const Model& m, bool adjoint, int dtype, const void* in, void* out, void* buf,
                  hipStream_t st) {
   const Layout& lay = layout_for(m, adjoint, dtype);
@@ -1002,7 +1157,7 @@ int launch_apply(const Model& m, bool adjoint, int dtype, const void* in, void* 
     if (dtype == AROAM_FP32)
       AROAM_TRY((launch_staged<float, 1>(lay, pk, buf, partial, out, st)));
     else
-      AROAM_TRY((launch_staged<uint16_t, kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
+      AROAM_TRY((launch_split<kTileRows8 / 16>(lay, pk, buf, partial, out, st)));
   }
   AROAM_HIP(hipGetLastError());
   return AROAM_OK;
