@@ -140,6 +140,23 @@ def test_quantized_applies_match_reference_elementwise(name, dtype):
                 f"{name} {dtype} adjoint", rel_l2(xa, oops.adjoint(H, y)))
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_quantized_elementwise_cases_include_cut_layouts(dtype):
+    """The element-wise cases above cover the kernels' partial-slot path: on these grids the
+    launch planner cuts some reduced-precision tiles into pieces (the split BF16 / FP8 kernels
+    then write partial sums that the slot-sum kernel adds), so a mistake in that path fails
+    the element-wise comparison."""
+    d = P.DTYPES[dtype]
+    cut = []
+    for name in SMALL:
+        info = gpu_model(name).info()
+        for kind, tiles in (("pieces", "row_tiles"), ("pieces_adj", "row_tiles_adj")):
+            if info[kind][d] > info[tiles][d]:
+                cut.append(f"{name} {kind} {info[kind][d]}/{info[tiles][d]}")
+    print(f"[{dtype}] cut layouts: {cut}", flush=True)
+    assert cut, f"no {dtype} layout of {SMALL} is cut"
+
+
 @functools.lru_cache(maxsize=None)
 def window400_blocks():
     """Oracle table of the 400x400 / 5 um / K = 40 workload at two whole 16-depth blocks (one
