@@ -221,6 +221,17 @@ __device__ __forceinline__ void read_x(const T* lds, const int (&lbase)[NT], int
     if (t % TPR < NTC) x[t] = *reinterpret_cast<const u32x4*>(lds + lbase[t] + mo);
 }
 
+// read_x for a lane whose tile t sits at row base rb[t / TPR] plus column offset
+// (t % TPR) * 16 * CSC (compile-time column stride CSC, so the offsets are immediates).
+template <typename T, int NT, int TPR, int CSC, int NR>
+__device__ __forceinline__ void read_x_rows(const T* lds, const int (&rb)[NR], int mo,
+                                            u32x4 (&x)[NT]) {
+  mo &= (1 << kMetaMaskShift) - 1;  // the top bits hold the bundle's mask
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    x[t] = *reinterpret_cast<const u32x4*>(lds + rb[t / TPR] + mo + (t % TPR) * 16 * CSC);
+}
+
 // MFMAs of one bundle whose position fragments are already in registers (tiles as read_x).
 template <typename T, int MH, int NT, int TPR = 1, int NTC = TPR>
 __device__ __forceinline__ void bundle_mma(const AFrag<T, MH>& f, const u32x4 (&xraw)[NT],
@@ -431,6 +442,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   static_assert(4 % S == 0 && BR % P == 0 && NT % S == 0, "split shape");
   constexpr int PF = 2;         // prefetched stage vectors per thread
   constexpr int PD = 2;         // table-fragment ring depth
+  constexpr int CSC = kColumnBytes / 2;  // LDS column stride (elements; checked at launch)
   constexpr int CH = 4 * VEC;
   const int4 piece = a.pieces[blockIdx.y];
   const int tile = piece.x;
@@ -465,19 +477,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     for (int u = u0; u < u1; ++u) {
       const int4 U = a.units[u];
       const int R = U.x + a.K;
-      int lbase[NT];
+      // LDS base of this lane's position in each of the wave's rows for the unit's row offset
+      // (eight row bases instead of sixteen tile bases: fewer VGPRs, 3-4 % faster)
+      int rb[RW];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int r = grp * RW + t / TPR, c = (t % TPR) * 16 + n;
-        lbase[t] = (((r + R) % RS) * a.NCOL + c) * a.CS;
-      }
+      for (int r = 0; r < RW; ++r) rb[r] = (((grp * RW + r + R) % RS) * a.NCOL + n) * CSC;
       for (int b0 = U.z + sw; b0 < U.w; b0 += S * PD) {
 #pragma unroll
         for (int j = 0; j < PD; ++j) {
           const int b = b0 + S * j;
           if (b < U.w) {
             u32x4 x[NT];
-            read_x<T, NT>(lds, lbase, ring[j].mo, x);
+            read_x_rows<T, NT, TPR, CSC>(lds, rb, ring[j].mo, x);
             bundle_mma<T, MH, NT>(ring[j], x, acc);
           }
           load_a<T, MH>(pack_raw, a.meta, min(b + S * PD, U.w - 1), g, n, ring[j]);
@@ -1029,6 +1040,7 @@ int launch_split(const Layout& lay, const Pack& pk, const void* buf, float* part
   AROAM_TRY(allow_full_lds(kern, attr_set));
   StagedArgs a;
   AROAM_TRY(staged_args(lay, partial, 2, a));
+  AROAM_CHECK(lay.CS * 2 == kColumnBytes, AROAM_EINVAL, "BF16 layout column stride mismatch");
   const size_t lds = std::max(lay.lds_bytes, red_bytes(kSplit, MH));
   const dim3 grid((unsigned)lay.n_patches, (unsigned)lay.n_pieces);
   hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, (const void*)pk.d, (const uint16_t*)buf,
