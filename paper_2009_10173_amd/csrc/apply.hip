@@ -795,7 +795,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   static_assert(4 % S == 0 && BR % P == 0 && NT % S == 0 && NT % XP == 0, "split shape");
   constexpr int NX = NT / XP;          // tiles per position-fragment read phase
   constexpr int PF = 2;
-  constexpr int RQ = 4;                // record ring depth (a multiple of PD)
+  constexpr int RQ = 2;                // record ring depth (a multiple of PD; 4 measured slower)
   constexpr int MH = 2;
   const int4 piece = a.pieces[blockIdx.y];
   const int tile = piece.x;
